@@ -1,0 +1,175 @@
+/*
+ * rbc.h - C ABI of the MI355X library for Parareal applied to 2D
+ * Rayleigh-Benard convection (Clarke, Davies, Ruprecht, Tobias & Oishi,
+ * "Performance of parallel-in-time integration for Rayleigh Benard
+ * Convection").
+ *
+ * The library advances the Oberbeck-Boussinesq equations (section 2.1,
+ * Eqs. 1-4) on a Fourier(x) x Chebyshev(z) grid (section 3.2) with
+ * implicit-explicit Runge-Kutta steps (sections 3.2 and 3.6), on every
+ * Parareal time slice at once, and runs the Parareal iteration (section
+ * 3.1, Eq. 13) around it on the device.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns rbc_status; nothing throws across the ABI.
+ *    Negative values are errors (outputs undefined), positive values are
+ *    warnings with valid outputs.  rbc_last_error() describes the last one.
+ *  - Units are free-fall units on z in [0, Lz]: viscosity sqrt(Pr/Ra),
+ *    thermal diffusivity 1/sqrt(Ra Pr), buoyancy coefficient 1.  The
+ *    paper writes Eqs. 1-3 in thermal-diffusion units on z in [-1/2, 1/2];
+ *    the two differ only by the time and velocity scales.
+ *  - A state is one time level of one run, FP64, laid out as
+ *        [field][m][re, im][n]
+ *    field 0 = streamfunction psi_m for Fourier modes m >= 1, and for
+ *    m = 0 the mean horizontal velocity u_bar(z) (imaginary part zero);
+ *    field 1 = temperature T_m.  m = 0..Nx/2-1 (the Nyquist mode is
+ *    dropped), n = 0..Nz-1 are Chebyshev-T coefficients in
+ *    zeta = 2 z / Lz - 1 (z = 0, the hot wall, is zeta = -1).  A field
+ *    value is f(x, z) = f_0(z) + 2 Re sum_{m>=1} f_m(z) exp(2 pi i m x / Lx).
+ *    rbc_state_size() gives the number of doubles, 4 * (Nx/2) * Nz.
+ *    Arrays of states are contiguous: [slice][state].
+ *  - Device pointers are caller-owned memory on the handle's device (for
+ *    example torch tensors: pass data_ptr()).  The handle owns every
+ *    workspace, sized once at rbc_create.
+ *  - Calls are enqueued on the handle's HIP stream and return without
+ *    waiting, except those that return host values (rbc_nusselt,
+ *    parareal_iterate, rbc_coarse_sweep with a host defect pointer),
+ *    which synchronise the stream.  A handle is not thread-safe.
+ */
+#ifndef RBC_H
+#define RBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbc_ctx* rbc_handle;
+
+typedef enum {
+  RBC_OK = 0,
+  RBC_NOT_CONVERGED = 1,    /* k_max reached with the defect above tol      */
+  RBC_ERR_ARG = -1,         /* bad size, null pointer, unsupported grid      */
+  RBC_ERR_OOM = -2,         /* device allocation failed at create            */
+  RBC_ERR_HIP = -3,         /* a HIP runtime call failed                     */
+  RBC_ERR_NONFINITE = -4,   /* NaN/Inf in an iterate (buffers kept as-is)    */
+  RBC_ERR_STATE = -5        /* factorisation check failed / bad handle state */
+} rbc_status;
+
+typedef enum { RBC_FP64 = 0, RBC_MIXED = 1 } rbc_precision;
+typedef enum { RBC_ARS222 = 2, RBC_ARS443 = 4 } rbc_scheme;
+
+/* Problem and discretisation.  Section 2.1 gives the equations and the
+ * box (aspect ratio 2), section 3.2 the grid, sections 3.6-3.7 the coarse
+ * propagator and the iteration. */
+typedef struct {
+  double Ra, Pr;           /* Rayleigh and Prandtl numbers                  */
+  double Lx, Lz;           /* box size                                      */
+  int32_t Nx, Nz;          /* fine grid: Nx % 4 == 0, Nz % 2 == 0, Nz >= 8 */
+  int32_t Nx_c, Nz_c;      /* coarse grid (<= fine, same rules)             */
+  double t0, t_end;        /* time window split into n_slices slices        */
+  int32_t n_slices;        /* Parareal slices (>= 1)                        */
+  double dt_f, dt_c;       /* requested steps; each slice uses
+                              dT / ceil(dT / dt) so slices hold whole steps */
+  int32_t scheme_f, scheme_c;   /* rbc_scheme                              */
+  int32_t precision;       /* rbc_precision: RBC_FP64, or RBC_MIXED = FP32
+                              transforms, products and stage history of
+                              the explicit terms; FP64 state, implicit
+                              solves, correction, defect and Nusselt       */
+  int32_t nu_stride;       /* sample Nu every nu_stride fine steps; 0 = off */
+  double nu_t_start;       /* start of the Nu time-average window           */
+  double T_bot, T_top;     /* wall temperatures at z = 0 and z = Lz (Eq. 4) */
+} rbc_params;
+
+/* Fill p with defaults (T_bot = 1, T_top = 0, ARS443, FP64, no sampling). */
+rbc_status rbc_default_params(rbc_params* p);
+
+/* Device bytes rbc_create would allocate for p (admission control). */
+rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes);
+
+/* Validate p, build the operator tables and band factorisations on the
+ * host, allocate workspaces on the current device; hip_stream may be NULL
+ * (the null stream).  On error *out is NULL. */
+rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out);
+rbc_status rbc_destroy(rbc_handle h);
+
+/* Description of the last error on h (NULL h: the last create error). */
+const char* rbc_last_error(rbc_handle h);
+
+/* Doubles per state on the fine (coarse = 0) or coarse (coarse = 1) grid. */
+rbc_status rbc_state_size(rbc_handle h, int32_t coarse, size_t* n_doubles);
+
+/* Steps per slice and the step actually used on the fine or coarse grid. */
+rbc_status rbc_steps_per_slice(rbc_handle h, int32_t coarse, int32_t* n_steps, double* dt);
+
+/* Initial state of section 2.1 (linear profile plus small perturbation,
+ * no flow): T = T_bot + (T_top - T_bot) z/Lz + amp xi z (Lz - z)/Lz^2 on
+ * the Nx x Nz collocation grid (x_i = i Lx/Nx, Chebyshev-Gauss z points),
+ * transformed to coefficients; psi = u_bar = 0.  xi[ix][iz] are standard
+ * normals: point p = ix*Nz + iz uses SplitMix64 outputs 2p and 2p+1 of
+ * the stream started at seed as uniforms u1, u2 (top 53 bits), and
+ * xi = sqrt(-2 ln(1 - u1)) cos(2 pi u2).  Writes one fine state. */
+rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double noise_amp, double* U0_dev);
+
+/* The fine propagator F on a batch of slices (the data-parallel half of
+ * Eq. 13): n_steps IMEX steps of the fine grid on each of n_slices
+ * independent states.  U_in and U_out are [n_slices][state] (they may be
+ * the same pointer).  If nu_samples_dev is not NULL and nu_stride > 0 it
+ * receives [n_slices][n_steps / nu_stride][3] = (Nu_V, Nu_b, Nu_t) after
+ * every nu_stride-th step.  n_slices <= the handle's n_slices. */
+rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in_dev, double* U_out_dev,
+                               int32_t n_slices, int32_t n_steps, double* nu_samples_dev);
+
+/* The serial coarse sweep of Eq. 13 (G = prolong o coarse steps o restrict,
+ * restriction = keep the first Nx_c/2 modes and Nz_c coefficients,
+ * prolongation = zero-pad).  U_dev is [n_slices + 1][state];
+ * G_dev is [n_slices][coarse state].
+ *  mode 0 (predict):  for n = first_slice..S-1:
+ *      g = G(U_n); U_{n+1} = g; G_n = coarse part of g.
+ *  mode 1 (correct):  for n = first_slice..S-1:
+ *      g = G(U_n); U_{n+1} = g + F_n - G_n; G_n = coarse part of g,
+ *      with F_dev = [n_slices][state] the fine results of the last iteration.
+ * If defect_host is not NULL it receives max_n ||U_{n+1}^new - U_{n+1}^old||
+ * / ||U_{n+1}^new|| over the updated slices (the call then synchronises). */
+rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first_slice,
+                            double* U_dev, const double* F_dev, double* G_dev,
+                            double* defect_host);
+
+/* Parareal (section 3.1, Eq. 13) on the device.  U_dev is [n_slices+1][state];
+ * on entry U_dev[0] is the initial state, on return U_dev[n] = U_n^K.
+ * Iteration 0 is the coarse prediction.  Iteration k runs F on slices
+ * k-1..S-1 (the earlier ones are already exact), then the coarse
+ * correction sweep; its defect (section 3.7) is the maximum over slices of
+ * the relative L2 change of the state vector.  Stops when the defect is
+ * <= tol, at k = k_max, or at k = n_slices (then U equals the serial fine
+ * solution).  defect_hist_host[k-1] gets the defect of iteration k
+ * (k_max entries).  nu_avg_hist_host, if not NULL and nu_stride > 0,
+ * gets [k_max + 1][3]: the time average over [nu_t_start, t_end] of
+ * (Nu_V, Nu_b, Nu_t) along the trajectories of iteration k (k = 0: the
+ * coarse trajectory).  Returns RBC_NOT_CONVERGED if stopped by k_max with
+ * the defect above tol > 0, RBC_ERR_NONFINITE on NaN/Inf. */
+rbc_status parareal_iterate(rbc_handle h, double* U_dev, int32_t k_max, double tol,
+                            int32_t* k_done_host, double* defect_hist_host,
+                            double* nu_avg_hist_host);
+
+/* Nusselt numbers of section 2.2 for n_states fine states (Eqs. 8-10):
+ * nu_host[i] = (Nu_V, Nu_b, Nu_t).  Nu_b, Nu_t: -dT/dz of the horizontal
+ * mean at z = 0 and z = Lz.  Nu_V: volume mean of -dT/dz + sqrt(Ra Pr) w T,
+ * integrated exactly for the discrete fields.  Synchronises. */
+rbc_status rbc_nusselt(rbc_handle h, const double* U_dev, int32_t n_states, double* nu_host);
+
+/* Diagnostic: the explicit (advective) terms of one fine state in the
+ * equations' bases: E_dev gets a state-shaped array whose field 0 holds
+ * -S3S2S1S0 N_omega (m >= 1) and -S1 D1 <u w> (m = 0), field 1 holds
+ * -S1S0 N_T, for the equation rows (the last 4 / 2 rows are zero). */
+rbc_status rbc_explicit_terms(rbc_handle h, const double* U_dev, double* E_dev);
+
+/* Wait for all work enqueued on the handle's stream. */
+rbc_status rbc_synchronize(rbc_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBC_H */

@@ -1,0 +1,458 @@
+// C ABI of librbc (include/rbc.h): handle management, the seeded initial
+// state, the fine propagator over a batch of slices, the serial coarse sweep
+// and the Parareal iteration of Eq. 13 (section 3.1 of the paper), driven from
+// the host with every arithmetic step in the HIP kernels.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rbc_internal.hpp"
+
+struct rbc_ctx {
+  rbc_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  rbc::GridPlan fine, coarse;
+  rbc::Work wf, wc;
+  int nf = 0, nc = 0;          // steps per slice
+  double* Xc = nullptr;        // coarse state being advanced
+  double* Fbuf = nullptr;      // [S][state]   F(U_n^(k-1))
+  double* Gbuf = nullptr;      // [S][cstate]  coarse part of G(U_n^k)
+  double* part = nullptr;      // [S+1][kCombineBlocks][2]
+  double* dscal = nullptr;     // [2] defect, non-finite flag
+  double* nu_f = nullptr;      // [S][nsf][3]
+  double* nu_c = nullptr;      // [S][nsc][3]
+  int nsf = 0, nsc = 0, stride_c = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+rbc_status fail(rbc_handle h, rbc_status s, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_err = msg;
+  return s;
+}
+
+#define HIPCHK(h, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((h), RBC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+int steps_for(double t0, double t1, int S, double dt, double* dt_used) {
+  const double dT = (t1 - t0) / S;
+  int n = int(std::ceil(dT / dt - 1e-9));
+  if (n < 1) n = 1;
+  *dt_used = dT / n;
+  return n;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+std::string check_params(const rbc_params* p) {
+  if (!p) return "params is NULL";
+  if (!(p->Ra > 0) || !(p->Pr > 0) || !(p->Lx > 0) || !(p->Lz > 0)) return "Ra, Pr, Lx, Lz must be > 0";
+  if (!pow2(p->Nx) || p->Nx < 4 || !pow2(p->Nx_c) || p->Nx_c < 4)
+    return "Nx and Nx_c must be powers of two >= 4 (padded grid 3 Nx / 2)";
+  if (p->Nz < 8 || p->Nz % 2 || p->Nz_c < 8 || p->Nz_c % 2) return "Nz and Nz_c must be even and >= 8";
+  if (p->Nz > 512 || p->Nx > 8192) return "grid too large (Nz <= 512, Nx <= 8192)";
+  if (p->Nx_c > p->Nx || p->Nz_c > p->Nz) return "coarse grid must not exceed the fine grid";
+  if (p->n_slices < 1) return "n_slices must be >= 1";
+  if (!(p->t_end > p->t0)) return "t_end must exceed t0";
+  if (!(p->dt_f > 0) || !(p->dt_c > 0)) return "dt_f, dt_c must be > 0";
+  for (int s : {p->scheme_f, p->scheme_c})
+    if (s != RBC_ARS222 && s != RBC_ARS443) return "scheme must be RBC_ARS222 or RBC_ARS443";
+  if (p->precision != RBC_FP64 && p->precision != RBC_MIXED) return "precision must be RBC_FP64 or RBC_MIXED";
+  if (p->nu_stride < 0) return "nu_stride must be >= 0";
+  return "";
+}
+
+void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
+  g.Nx = coarse ? p->Nx_c : p->Nx;
+  g.Nz = coarse ? p->Nz_c : p->Nz;
+  g.Mx = g.Nx / 2;
+  g.Px = 3 * g.Nx / 2;
+  g.Pz = 3 * g.Nz / 2;
+  g.n = g.Nz / 2;
+  g.Ra = p->Ra; g.Pr = p->Pr; g.Lx = p->Lx; g.Lz = p->Lz;
+  g.dt = dt;
+  g.T_bot = p->T_bot; g.T_top = p->T_top;
+  g.scheme = coarse ? p->scheme_c : p->scheme_f;
+  g.mixed = (p->precision == RBC_MIXED);
+  g.MT = (g.Nz >= 128) ? 4 : 8;
+  // modes per block of the per-mode kernel; RBC_MODE_TILE overrides (1..32)
+  if (const char* e = std::getenv("RBC_MODE_TILE")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 32) g.MT = v;
+  }
+  if (g.MT > g.Mx) g.MT = g.Mx;
+}
+
+size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::GridPlan& c, int nsf, int nsc) {
+  const size_t S = p->n_slices;
+  size_t b = 0;
+  b += size_t(4) * c.Mx * c.Nz * 8;                 // Xc
+  b += S * 4 * f.Mx * f.Nz * 8;                     // F
+  b += S * 4 * c.Mx * c.Nz * 8;                     // G
+  b += (S + 1) * rbc::kCombineBlocks * 2 * 8 + 64;  // partials, scalars
+  b += S * size_t(nsf) * 3 * 8 + S * size_t(nsc) * 3 * 8;
+  return b;
+}
+
+void release(rbc_handle h) {
+  if (!h) return;
+  rbc::free_work(h->wf);
+  rbc::free_work(h->wc);
+  for (void* q : {(void*)h->Xc, (void*)h->Fbuf, (void*)h->Gbuf, (void*)h->part, (void*)h->dscal,
+                  (void*)h->nu_f, (void*)h->nu_c, h->fine.d_tables, h->coarse.d_tables})
+    if (q) (void)hipFree(q);
+}
+
+// Sample counts and the coarse sampling stride.
+void sampling(const rbc_params* p, int nf, int nc, double dtf, double dtc, int* nsf, int* nsc, int* sc) {
+  if (p->nu_stride <= 0) {
+    *nsf = *nsc = *sc = 0;
+    return;
+  }
+  *nsf = nf / p->nu_stride;
+  int s = int(std::lround(p->nu_stride * dtf / dtc));
+  if (s < 1) s = 1;
+  *sc = s;
+  *nsc = nc / s;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbc_status rbc_default_params(rbc_params* p) {
+  if (!p) return RBC_ERR_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->Ra = 1e4; p->Pr = 1; p->Lx = 2; p->Lz = 1;
+  p->Nx = 64; p->Nz = 32; p->Nx_c = 64; p->Nz_c = 32;
+  p->t0 = 0; p->t_end = 1; p->n_slices = 1;
+  p->dt_f = 1e-3; p->dt_c = 1e-2;
+  p->scheme_f = RBC_ARS443; p->scheme_c = RBC_ARS443;
+  p->precision = RBC_FP64;
+  p->nu_stride = 0; p->nu_t_start = 0;
+  p->T_bot = 1; p->T_top = 0;
+  return RBC_OK;
+}
+
+rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes) {
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(nullptr, RBC_ERR_ARG, e);
+  if (!device_bytes) return fail(nullptr, RBC_ERR_ARG, "device_bytes is NULL");
+  rbc::GridPlan f, c;
+  double dtf, dtc;
+  int nf = steps_for(p->t0, p->t_end, p->n_slices, p->dt_f, &dtf);
+  int nc = steps_for(p->t0, p->t_end, p->n_slices, p->dt_c, &dtc);
+  setup_grid(f, p, false, dtf);
+  setup_grid(c, p, true, dtc);
+  f.tab = rbc::make_tableau(f.scheme);
+  c.tab = rbc::make_tableau(c.scheme);
+  // plan sizes without building the factorisations
+  auto tables = [](const rbc::GridPlan& g) {
+    size_t n = g.Nz / 2, rb = g.mixed ? 4 : 8;
+    size_t d = 2 * n * 14 + size_t(g.Mx) * 2 * (rbc::kFacT * n + 4) + size_t(g.Mx) * 2 * (rbc::kFacP * n + 4);
+    size_t r = size_t(4) * (g.Pz / 2) * g.Nz + size_t(3) * g.Nz * (g.Pz / 2) + 2 * size_t(g.Px);
+    return d * 8 + r * rb + 16 * 256;
+  };
+  int nsf, nsc, sc;
+  sampling(p, nf, nc, dtf, dtc, &nsf, &nsc, &sc);
+  *device_bytes = tables(f) + tables(c) + rbc::work_bytes(f, p->n_slices) + rbc::work_bytes(c, 1) +
+                  pararea_bytes(p, f, c, nsf, nsc);
+  return RBC_OK;
+}
+
+rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
+  if (!out) return fail(nullptr, RBC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(nullptr, RBC_ERR_ARG, e);
+  rbc_handle h = new (std::nothrow) rbc_ctx();
+  if (!h) return fail(nullptr, RBC_ERR_OOM, "host allocation failed");
+  h->p = *p;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  double dtf, dtc;
+  h->nf = steps_for(p->t0, p->t_end, p->n_slices, p->dt_f, &dtf);
+  h->nc = steps_for(p->t0, p->t_end, p->n_slices, p->dt_c, &dtc);
+  setup_grid(h->fine, p, false, dtf);
+  setup_grid(h->coarse, p, true, dtc);
+  e = rbc::build_plan(h->fine);
+  if (e.empty()) e = rbc::build_plan(h->coarse);
+  if (!e.empty()) {
+    delete h;
+    return fail(nullptr, RBC_ERR_STATE, e);
+  }
+  sampling(p, h->nf, h->nc, dtf, dtc, &h->nsf, &h->nsc, &h->stride_c);
+  hipError_t he = hipGetDevice(&h->device);
+  auto bail = [&](rbc_status st, const std::string& m) {
+    release(h);
+    delete h;
+    return fail(nullptr, st, m);
+  };
+  if (he != hipSuccess) return bail(RBC_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  if ((he = rbc::upload_plan(h->fine)) != hipSuccess || (he = rbc::upload_plan(h->coarse)) != hipSuccess)
+    return bail(RBC_ERR_OOM, std::string("table upload: ") + hipGetErrorString(he));
+  if ((he = rbc::alloc_work(h->fine, p->n_slices, h->wf)) != hipSuccess ||
+      (he = rbc::alloc_work(h->coarse, 1, h->wc)) != hipSuccess)
+    return bail(RBC_ERR_OOM, std::string("workspace: ") + hipGetErrorString(he));
+  const size_t S = p->n_slices;
+  const size_t fs = h->fine.dev.state, cs = h->coarse.dev.state;
+  if (hipMalloc((void**)&h->Xc, cs * 8) != hipSuccess || hipMalloc((void**)&h->Fbuf, S * fs * 8) != hipSuccess ||
+      hipMalloc((void**)&h->Gbuf, S * cs * 8) != hipSuccess ||
+      hipMalloc((void**)&h->part, (S + 1) * rbc::kCombineBlocks * 2 * 8) != hipSuccess ||
+      hipMalloc((void**)&h->dscal, 64) != hipSuccess)
+    return bail(RBC_ERR_OOM, "parareal buffers");
+  if (h->nsf > 0 && hipMalloc((void**)&h->nu_f, S * h->nsf * 3 * 8) != hipSuccess)
+    return bail(RBC_ERR_OOM, "nu sample buffer");
+  if (h->nsc > 0 && hipMalloc((void**)&h->nu_c, S * h->nsc * 3 * 8) != hipSuccess)
+    return bail(RBC_ERR_OOM, "nu sample buffer");
+  *out = h;
+  return RBC_OK;
+}
+
+rbc_status rbc_destroy(rbc_handle h) {
+  if (!h) return RBC_ERR_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+  return RBC_OK;
+}
+
+const char* rbc_last_error(rbc_handle h) { return h ? h->err.c_str() : g_create_err.c_str(); }
+
+rbc_status rbc_state_size(rbc_handle h, int32_t coarse, size_t* n) {
+  if (!h || !n) return fail(h, RBC_ERR_ARG, "null argument");
+  *n = coarse ? h->coarse.dev.state : h->fine.dev.state;
+  return RBC_OK;
+}
+
+rbc_status rbc_steps_per_slice(rbc_handle h, int32_t coarse, int32_t* n_steps, double* dt) {
+  if (!h || !n_steps || !dt) return fail(h, RBC_ERR_ARG, "null argument");
+  *n_steps = coarse ? h->nc : h->nf;
+  *dt = coarse ? h->coarse.dt : h->fine.dt;
+  return RBC_OK;
+}
+
+rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double amp, double* U0) {
+  if (!h || !U0) return fail(h, RBC_ERR_ARG, "null argument");
+  const rbc::GridPlan& g = h->fine;
+  const int Nx = g.Nx, Nz = g.Nz, Mx = g.Mx;
+  // seeded noise: SplitMix64 outputs 2p, 2p+1 -> Box-Muller (cosine branch)
+  auto mix = [seed](uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto unif = [&](uint64_t c) { return double(mix(c) >> 11) * (1.0 / 9007199254740992.0); };
+  std::vector<double> Tg(size_t(Nx) * Nz), zj(Nz);
+  for (int j = 0; j < Nz; ++j) zj[j] = (std::cos(M_PI * (j + 0.5) / Nz) + 1.0) * 0.5;   // z / Lz
+  for (int ix = 0; ix < Nx; ++ix)
+    for (int iz = 0; iz < Nz; ++iz) {
+      const uint64_t pidx = uint64_t(ix) * Nz + iz;
+      const double u1 = unif(2 * pidx), u2 = unif(2 * pidx + 1);
+      const double xi = std::sqrt(-2.0 * std::log(1.0 - u1)) * std::cos(2.0 * M_PI * u2);
+      const double z = zj[iz];
+      Tg[size_t(ix) * Nz + iz] = g.T_bot + (g.T_top - g.T_bot) * z + amp * xi * z * (1.0 - z);
+    }
+  // Fourier in x (modes m < Mx, 1/Nx normalisation), Chebyshev in z
+  std::vector<double> cs(Nx), sn(Nx);
+  for (int t = 0; t < Nx; ++t) {
+    cs[t] = std::cos(2.0 * M_PI * t / Nx);
+    sn[t] = std::sin(2.0 * M_PI * t / Nx);
+  }
+  std::vector<double> U(size_t(4) * Mx * Nz, 0.0), fr(Nz), fi(Nz);
+  std::vector<double> Tc(size_t(Nz) * Nz);
+  for (int n = 0; n < Nz; ++n)
+    for (int j = 0; j < Nz; ++j) Tc[size_t(n) * Nz + j] = (n == 0 ? 1.0 : 2.0) / Nz * std::cos(n * M_PI * (j + 0.5) / Nz);
+  for (int m = 0; m < Mx; ++m) {
+    for (int j = 0; j < Nz; ++j) {
+      double ar = 0, ai = 0;
+      for (int ix = 0; ix < Nx; ++ix) {
+        const int t = int((int64_t(m) * ix) % Nx);
+        ar += Tg[size_t(ix) * Nz + j] * cs[t];
+        ai -= Tg[size_t(ix) * Nz + j] * sn[t];
+      }
+      fr[j] = ar / Nx;
+      fi[j] = (m == 0) ? 0.0 : ai / Nx;
+    }
+    for (int n = 0; n < Nz; ++n) {
+      double cr = 0, ci = 0;
+      for (int j = 0; j < Nz; ++j) {
+        cr += Tc[size_t(n) * Nz + j] * fr[j];
+        ci += Tc[size_t(n) * Nz + j] * fi[j];
+      }
+      U[((size_t(1) * Mx + m) * 2 + 0) * Nz + n] = cr;
+      U[((size_t(1) * Mx + m) * 2 + 1) * Nz + n] = ci;
+    }
+  }
+  HIPCHK(h, hipMemcpyAsync(U0, U.data(), U.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RBC_OK;
+}
+
+rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in, double* U_out, int32_t n_slices, int32_t n_steps,
+                               double* nu_samples) {
+  if (!h || !U_in || !U_out) return fail(h, RBC_ERR_ARG, "null argument");
+  if (n_slices < 1 || n_slices > h->p.n_slices) return fail(h, RBC_ERR_ARG, "n_slices out of range");
+  if (n_steps < 0) return fail(h, RBC_ERR_ARG, "n_steps < 0");
+  const size_t bytes = size_t(n_slices) * h->fine.dev.state * 8;
+  if (U_in != U_out) HIPCHK(h, hipMemcpyAsync(U_out, U_in, bytes, hipMemcpyDeviceToDevice, h->stream));
+  const int stride = h->p.nu_stride;
+  const int ld = (nu_samples && stride > 0) ? n_steps / stride : 0;
+  HIPCHK(h, rbc::launch_steps(h->fine, h->wf, U_out, n_slices, n_steps, ld > 0 ? nu_samples : nullptr, stride,
+                              ld, h->stream));
+  return RBC_OK;
+}
+
+namespace {
+
+// Coarse sweep over slices [first, S): see rbc_coarse_sweep.  Coarse Nu
+// samples of slice n go to nu_c[n] when requested.
+rbc_status sweep(rbc_handle h, int mode, int first, double* U, const double* F, double* G, bool with_nu) {
+  const int S = h->p.n_slices;
+  const size_t fs = h->fine.dev.state, cs = h->coarse.dev.state;
+  for (int n = first; n < S; ++n) {
+    HIPCHK(h, rbc::launch_restrict(h->fine, h->coarse, U + n * fs, h->Xc, h->stream));
+    double* nu = (with_nu && h->nu_c) ? h->nu_c + size_t(n) * h->nsc * 3 : nullptr;
+    HIPCHK(h, rbc::launch_steps(h->coarse, h->wc, h->Xc, 1, h->nc, nu, h->stride_c, h->nsc, h->stream));
+    HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, mode, U + (n + 1) * fs, mode == 1 ? F + n * fs : nullptr,
+                                  h->Xc, G + n * cs, h->part + size_t(n + 1) * rbc::kCombineBlocks * 2,
+                                  h->stream));
+  }
+  return RBC_OK;
+}
+
+rbc_status read_defect(rbc_handle h, int first, int last, double* defect, bool* bad) {
+  HIPCHK(h, rbc::launch_defect(h->part, first, last, h->dscal, h->stream));
+  double v[2];
+  HIPCHK(h, hipMemcpyAsync(v, h->dscal, 16, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *defect = v[0];
+  *bad = v[1] != 0.0;
+  return RBC_OK;
+}
+
+// Time average of the Nu samples of slices [0, S) over [nu_t_start, t_end].
+rbc_status nu_average(rbc_handle h, const double* dev, int ns, int stride, double dt, double* out3) {
+  const int S = h->p.n_slices;
+  std::vector<double> buf(size_t(S) * ns * 3);
+  HIPCHK(h, hipMemcpyAsync(buf.data(), dev, buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const double dT = (h->p.t_end - h->p.t0) / S;
+  double acc[3] = {0, 0, 0};
+  long cnt = 0;
+  for (int n = 0; n < S; ++n)
+    for (int q = 0; q < ns; ++q) {
+      const double t = h->p.t0 + n * dT + (q + 1) * stride * dt;
+      if (t < h->p.nu_t_start) continue;
+      for (int c = 0; c < 3; ++c) acc[c] += buf[(size_t(n) * ns + q) * 3 + c];
+      ++cnt;
+    }
+  for (int c = 0; c < 3; ++c) out3[c] = cnt ? acc[c] / cnt : NAN;
+  return RBC_OK;
+}
+
+}  // namespace
+
+rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first, double* U, const double* F, double* G,
+                            double* defect_host) {
+  if (!h || !U || !G) return fail(h, RBC_ERR_ARG, "null argument");
+  if (mode != 0 && mode != 1) return fail(h, RBC_ERR_ARG, "mode must be 0 (predict) or 1 (correct)");
+  if (mode == 1 && !F) return fail(h, RBC_ERR_ARG, "F is NULL in correct mode");
+  if (first < 0 || first > h->p.n_slices) return fail(h, RBC_ERR_ARG, "first_slice out of range");
+  rbc_status s = sweep(h, mode, first, U, F, G, false);
+  if (s != RBC_OK) return s;
+  if (defect_host) {
+    bool bad = false;
+    if ((s = read_defect(h, first + 1, h->p.n_slices + 1, defect_host, &bad)) != RBC_OK) return s;
+    if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in the coarse sweep");
+  }
+  return RBC_OK;
+}
+
+rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, int32_t* k_done,
+                            double* defect_hist, double* nu_hist) {
+  if (!h || !U || !k_done || !defect_hist) return fail(h, RBC_ERR_ARG, "null argument");
+  if (k_max < 0) return fail(h, RBC_ERR_ARG, "k_max < 0");
+  const int S = h->p.n_slices;
+  const size_t fs = h->fine.dev.state;
+  const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
+  rbc_status s;
+  *k_done = 0;
+  if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
+  if (want_nu) {
+    if (h->nsc > 0) {
+      if ((s = nu_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, nu_hist)) != RBC_OK) return s;
+    } else {
+      nu_hist[0] = nu_hist[1] = nu_hist[2] = NAN;
+    }
+  }
+  double defect = INFINITY;
+  int k = 0;
+  while (k < k_max && k < S) {
+    ++k;
+    // F on slices k-1..S-1 from U^(k-1)
+    const int na = S - (k - 1);
+    double* nu = want_nu ? h->nu_f + size_t(k - 1) * h->nsf * 3 : nullptr;
+    HIPCHK(h, hipMemcpyAsync(h->Fbuf + (k - 1) * fs, U + (k - 1) * fs, size_t(na) * fs * 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, rbc::launch_steps(h->fine, h->wf, h->Fbuf + (k - 1) * fs, na, h->nf, nu, h->p.nu_stride, h->nsf,
+                                h->stream));
+    // U_k^k = F(U_(k-1)^(k-1)) exactly; then the correction sweep
+    HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, 2, U + k * fs, h->Fbuf + (k - 1) * fs, nullptr, nullptr,
+                                  h->part + size_t(k) * rbc::kCombineBlocks * 2, h->stream));
+    if ((s = sweep(h, 1, k, U, h->Fbuf, h->Gbuf, false)) != RBC_OK) return s;
+    bool bad = false;
+    if ((s = read_defect(h, k, S + 1, &defect, &bad)) != RBC_OK) return s;
+    defect_hist[k - 1] = defect;
+    *k_done = k;
+    if (want_nu && (s = nu_average(h, h->nu_f, h->nsf, h->p.nu_stride, h->fine.dt, nu_hist + 3 * k)) != RBC_OK)
+      return s;
+    if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
+    if (defect <= tol) break;
+  }
+  if (k < S && !(defect <= tol) && tol > 0) return RBC_NOT_CONVERGED;
+  return RBC_OK;
+}
+
+rbc_status rbc_nusselt(rbc_handle h, const double* U, int32_t n, double* nu_host) {
+  if (!h || !U || !nu_host || n < 0) return fail(h, RBC_ERR_ARG, "bad argument");
+  if (n == 0) return RBC_OK;
+  double* d = nullptr;
+  HIPCHK(h, hipMallocAsync((void**)&d, size_t(n) * 3 * 8, h->stream));
+  hipError_t e = rbc::launch_nusselt(h->fine, U, n, d, 3, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(nu_host, d, size_t(n) * 3 * 8, hipMemcpyDeviceToHost, h->stream);
+  hipError_t e2 = hipFreeAsync(d, h->stream);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(h, RBC_ERR_HIP, std::string("rbc_nusselt: ") + hipGetErrorString(e));
+  return RBC_OK;
+}
+
+rbc_status rbc_explicit_terms(rbc_handle h, const double* U, double* E) {
+  if (!h || !U || !E) return fail(h, RBC_ERR_ARG, "null argument");
+  HIPCHK(h, hipMemsetAsync(E, 0, size_t(h->fine.dev.state) * 8, h->stream));
+  HIPCHK(h, rbc::launch_explicit(h->fine, h->wf, U, E, h->stream));
+  return RBC_OK;
+}
+
+rbc_status rbc_synchronize(rbc_handle h) {
+  if (!h) return RBC_ERR_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RBC_OK;
+}
+
+}  // extern "C"

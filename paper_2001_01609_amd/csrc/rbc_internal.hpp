@@ -1,0 +1,129 @@
+// Internal declarations of librbc: grid plans (host-built operator tables and
+// band factorisations), their device views, and the kernel launchers.
+//
+// Discretisation (section 3.2 of the paper): Fourier modes m = 0..Mx-1 in x,
+// Chebyshev-T coefficients n = 0..Nz-1 in z; products on the 3/2-padded
+// Px x Pz grid.  Equations (section 2.1) in streamfunction form, each written
+// in an ultraspherical basis (C^(2) rows for temperature and mean flow,
+// C^(4) rows for the streamfunction) so that every operator is banded; the
+// last 2 (or 4) rows are replaced by wall conditions (tau method).  Even and
+// odd coefficients decouple, so every system is split by parity p: half
+// index i stands for coefficient n = 2 i + p.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rbc.h"
+
+namespace rbc {
+
+constexpr int kMaxStages = 5;     // s + 1 stages of ARS(4,4,3)
+constexpr int kBlock = 256;       // threads per block of the per-mode kernels
+
+// Per-row entries of the stored factorisations (see build_factors()).
+constexpr int kFacT = 4;          // lm, 1/u_ii, u_i,i+1, v      (bordered tridiagonal)
+constexpr int kFacP = 7;          // lm1, lm2, 1/u_ii, u1, u2, v0, v1 (bordered pentadiagonal)
+
+// IMEX tableau in (s+1)-stage ARS form: stage 0 is the old solution.
+struct Tableau {
+  int s = 0;
+  double ae[kMaxStages][kMaxStages] = {};
+  double ai[kMaxStages][kMaxStages] = {};
+};
+Tableau make_tableau(int scheme);
+
+// Device view of one grid, passed to kernels by value.
+struct GridDev {
+  int Nx, Nz, Mx, Px, Pz, n;      // n = Nz / 2
+  int nrT, nrP;                   // band rows per parity: n - 1 (T, u_bar), n - 2 (psi)
+  int MT;                         // modes per block in the per-mode kernel
+  int state;                      // doubles per state = 4 Mx Nz
+  double kscale;                  // k_m = m * kscale
+  double nu, kappa, scale;        // viscosity, diffusivity, dzeta/dz = 2/Lz
+  double Lz, sqrtRaPr;
+  double T_bot, T_top;
+  const double* bS10;             // [2][n][3]  S1S0 rows, half offsets 0..2
+  const double* bD2;              // [2][n]     D2 rows, half offset 1
+  const double* bA;               // [2][n][3]  S3S2D2 rows, half offsets 1..3
+  const double* bB;               // [2][n][5]  S3S2S1S0 rows, half offsets 0..4
+  const double* bD4;              // [2][n]     D4 rows, half offset 2
+  const double* facT;             // [Mx][2][facT_stride]
+  const double* facP;             // [Mx][2][facP_stride]  (m = 0: u_bar eq, T layout)
+  int facT_stride, facP_stride;
+  const void* Winv;               // Real [4][Pz/2][Nz]: d^q T_n / dz^q at Gauss points
+  const void* Wfwd;               // Real [3][Nz][Pz/2]: folded forward maps (psi, T, u_bar rows)
+  const void* tw;                 // Real2 [Px]: exp(-2 pi i t / Px)
+  int nrad, rad[12];              // FFT radix plan for Px
+};
+
+// Host-side plan of one grid.
+struct GridPlan {
+  int Nx = 0, Nz = 0, Mx = 0, Px = 0, Pz = 0, n = 0;
+  double Ra = 0, Pr = 0, Lx = 0, Lz = 0, dt = 0, nu = 0, kappa = 0, scale = 0;
+  double T_bot = 1, T_top = 0;
+  int scheme = 4;
+  Tableau tab;
+  int MT = 8;
+  bool mixed = false;
+  // host tables
+  std::vector<double> bS10, bD2, bA, bB, bD4, facT, facP, Winv, Wfwd, tw;
+  int facT_stride = 0, facP_stride = 0;
+  double max_growth = 0;
+  // device copies
+  void* d_tables = nullptr;
+  GridDev dev{};
+};
+
+// Builds every host table of a grid; returns an empty string or an error.
+std::string build_plan(GridPlan& g);
+// Uploads the tables and fills g.dev.  Returns hipSuccess or the error.
+hipError_t upload_plan(GridPlan& g);
+size_t plan_device_bytes(const GridPlan& g);
+
+// Per-grid work buffers for a batch of `cap` slices.
+struct Work {
+  int cap = 0;
+  void* Q = nullptr;       // Real [cap][6][Pz][Mx][2]
+  void* Nh = nullptr;      // Real [cap][2][Pz][Mx][2]
+  void* qbar = nullptr;    // Real [cap][Pz]
+  void* Ehist = nullptr;   // Real [s][cap][state]
+  double* LYhist = nullptr;  // [s-1][cap][state]
+};
+size_t work_bytes(const GridPlan& g, int cap);
+hipError_t alloc_work(const GridPlan& g, int cap, Work& w);
+void free_work(Work& w);
+
+// ---- launchers (rbc_kernels.hip) -----------------------------------------
+// Advance n_slices contiguous states X in place by n_steps IMEX steps.  If
+// nu_out is not null, after every nu_stride-th step the Nusselt numbers of each
+// slice go to nu_out[s * nu_ld + sample][3].
+hipError_t launch_steps(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps,
+                        double* nu_out, int nu_stride, int nu_ld, hipStream_t st);
+// Explicit terms of one state (diagnostic): E = state-shaped FP64 array.
+hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st);
+// Nusselt numbers of n states: out[i*ld3 .. +3] (ld3 = stride in doubles).
+hipError_t launch_nusselt(const GridPlan& g, const double* X, int n, double* out, int ld3,
+                          hipStream_t st);
+// Fine -> coarse restriction (truncation).
+hipError_t launch_restrict(const GridPlan& f, const GridPlan& c, const double* Xf, double* Xc,
+                           hipStream_t st);
+// Parareal combination for one slice: mode 0 U = P(gc); 1 U = P(gc) + F - P(gold);
+// 2 U = F.  gold <- gc for modes 0 and 1.  Writes (||U_new - U_old||^2,
+// ||U_new||^2) block partials to part[kCombineBlocks][2].
+constexpr int kCombineBlocks = 64;
+hipError_t launch_combine(const GridPlan& f, const GridPlan& c, int mode, double* U,
+                          const double* F, const double* gc, double* gold, double* part,
+                          hipStream_t st);
+// Reduce partials of slices [first, last) (part is [S+1][kCombineBlocks][2]) into
+// out[0] = max relative defect, out[1] = non-finite flag (0/1).
+hipError_t launch_defect(const double* part, int first, int last, double* out, hipStream_t st);
+// Mean of Nu samples (n_rows rows of 3 doubles, rows in [row0, n_rows) used) -> out[3].
+hipError_t launch_nu_mean(const double* samples, int n_rows, const int* use, double* out,
+                          hipStream_t st);
+
+}  // namespace rbc

@@ -1,0 +1,196 @@
+"""Python binding of librbc (include/rbc.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device arrays
+are passed as torch tensors (float64, contiguous, on the GPU) or as raw
+integer device addresses; all arithmetic happens in the HIP library.  If
+the library has not been built, importing this module raises: there is no
+other implementation behind these names.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbc.so")
+
+RBC_OK = 0
+RBC_NOT_CONVERGED = 1
+RBC_ERR_ARG = -1
+RBC_ERR_OOM = -2
+RBC_ERR_HIP = -3
+RBC_ERR_NONFINITE = -4
+RBC_ERR_STATE = -5
+RBC_FP64 = 0
+RBC_MIXED = 1
+RBC_ARS222 = 2
+RBC_ARS443 = 4
+
+
+class RbcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rbc status {status}: {msg}")
+        self.status = status
+
+
+class rbc_params(ctypes.Structure):
+    _fields_ = [
+        ("Ra", ctypes.c_double), ("Pr", ctypes.c_double),
+        ("Lx", ctypes.c_double), ("Lz", ctypes.c_double),
+        ("Nx", ctypes.c_int32), ("Nz", ctypes.c_int32),
+        ("Nx_c", ctypes.c_int32), ("Nz_c", ctypes.c_int32),
+        ("t0", ctypes.c_double), ("t_end", ctypes.c_double),
+        ("n_slices", ctypes.c_int32),
+        ("dt_f", ctypes.c_double), ("dt_c", ctypes.c_double),
+        ("scheme_f", ctypes.c_int32), ("scheme_c", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("nu_stride", ctypes.c_int32),
+        ("nu_t_start", ctypes.c_double),
+        ("T_bot", ctypes.c_double), ("T_top", ctypes.c_double),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"librbc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, dbl, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int
+    sig = {
+        "rbc_default_params": (st, [P(rbc_params)]),
+        "rbc_query_footprint": (st, [P(rbc_params), P(ctypes.c_size_t)]),
+        "rbc_create": (st, [P(rbc_params), vp, P(vp)]),
+        "rbc_destroy": (st, [vp]),
+        "rbc_last_error": (ctypes.c_char_p, [vp]),
+        "rbc_state_size": (st, [vp, i32, P(ctypes.c_size_t)]),
+        "rbc_steps_per_slice": (st, [vp, i32, P(i32), P(dbl)]),
+        "rbc_init_state": (st, [vp, ctypes.c_uint64, dbl, vp]),
+        "rbc_fine_step_batch": (st, [vp, vp, vp, i32, i32, vp]),
+        "rbc_coarse_sweep": (st, [vp, i32, i32, vp, vp, vp, P(dbl)]),
+        "parareal_iterate": (st, [vp, vp, i32, dbl, P(i32), P(dbl), P(dbl)]),
+        "rbc_nusselt": (st, [vp, vp, i32, P(dbl)]),
+        "rbc_explicit_terms": (st, [vp, vp, vp]),
+        "rbc_synchronize": (st, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int, h=None) -> int:
+    if status < 0:
+        msg = _lib.rbc_last_error(h)
+        raise RbcError(status, msg.decode() if msg else "")
+    return status
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        if not x.is_cuda or str(x.dtype) != "torch.float64" or not x.is_contiguous():
+            raise ValueError("device arrays must be contiguous float64 CUDA/HIP tensors")
+        return x.data_ptr()
+    return int(x)
+
+
+def rbc_default_params() -> rbc_params:
+    p = rbc_params()
+    _check(_lib.rbc_default_params(ctypes.byref(p)))
+    return p
+
+
+def rbc_query_footprint(p: rbc_params) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.rbc_query_footprint(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def rbc_create(p: rbc_params, stream: Optional[int] = None):
+    h = ctypes.c_void_p()
+    _check(_lib.rbc_create(ctypes.byref(p), stream, ctypes.byref(h)))
+    return h
+
+
+def rbc_destroy(h) -> None:
+    _check(_lib.rbc_destroy(h), h)
+
+
+def rbc_last_error(h=None) -> str:
+    return (_lib.rbc_last_error(h) or b"").decode()
+
+
+def rbc_state_size(h, coarse: int = 0) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.rbc_state_size(h, coarse, ctypes.byref(n)), h)
+    return n.value
+
+
+def rbc_steps_per_slice(h, coarse: int = 0) -> Tuple[int, float]:
+    n, dt = ctypes.c_int32(), ctypes.c_double()
+    _check(_lib.rbc_steps_per_slice(h, coarse, ctypes.byref(n), ctypes.byref(dt)), h)
+    return n.value, dt.value
+
+
+def rbc_init_state(h, seed: int, noise_amp: float, U0) -> None:
+    _check(_lib.rbc_init_state(h, seed, noise_amp, _ptr(U0)), h)
+
+
+def rbc_fine_step_batch(h, U_in, U_out, n_slices: int, n_steps: int, nu_samples=None) -> None:
+    _check(_lib.rbc_fine_step_batch(h, _ptr(U_in), _ptr(U_out), n_slices, n_steps, _ptr(nu_samples)), h)
+
+
+def rbc_coarse_sweep(h, mode: int, first_slice: int, U, F, G, want_defect: bool = False):
+    d = ctypes.c_double()
+    _check(_lib.rbc_coarse_sweep(h, mode, first_slice, _ptr(U), _ptr(F), _ptr(G),
+                                 ctypes.byref(d) if want_defect else None), h)
+    return d.value if want_defect else None
+
+
+def parareal_iterate(h, U, k_max: int, tol: float, want_nu: bool = False):
+    """Returns (status, k_done, defects[k_done], nu_avg[k_done+1, 3] or None)."""
+    k = ctypes.c_int32()
+    defects = np.zeros(max(k_max, 1))
+    nu = np.full((k_max + 1, 3), np.nan) if want_nu else None
+    st = _check(_lib.parareal_iterate(
+        h, _ptr(U), k_max, tol, ctypes.byref(k),
+        defects.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_nu else None), h)
+    kd = k.value
+    return st, kd, defects[:kd].copy(), (nu[: kd + 1].copy() if want_nu else None)
+
+
+def rbc_nusselt(h, U, n_states: int) -> np.ndarray:
+    out = np.zeros((max(n_states, 1), 3))
+    _check(_lib.rbc_nusselt(h, _ptr(U), n_states,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
+    return out[:n_states]
+
+
+def rbc_explicit_terms(h, U, E) -> None:
+    _check(_lib.rbc_explicit_terms(h, _ptr(U), _ptr(E)), h)
+
+
+def rbc_synchronize(h) -> None:
+    _check(_lib.rbc_synchronize(h), h)
+
+
+def params_from_workload(w, **overrides) -> rbc_params:
+    """rbc_params for a rbc_inputs.Workload (field-by-field copy)."""
+    p = rbc_default_params()
+    p.Ra, p.Pr, p.Lx, p.Lz = w.Ra, w.Pr, w.Lx, w.Lz
+    p.Nx, p.Nz, p.Nx_c, p.Nz_c = w.Nx, w.Nz, w.Nx_c, w.Nz_c
+    p.t0, p.t_end, p.n_slices = w.t0, w.t_end, w.n_slices
+    p.dt_f, p.dt_c = w.dt_f, w.dt_c
+    p.scheme_f = p.scheme_c = w.scheme
+    p.precision = RBC_MIXED if w.mixed else RBC_FP64
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p

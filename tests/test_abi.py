@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/rbc.h declares, the Python struct matches the C layout,
+and argument validation rejects bad parameters before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbc.h")
+LIB = os.path.join(ROOT, "paper_2001_01609_amd", "librbc.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2001_01609_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:rbc_status|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    assert len(names) >= 14
+    return names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2001_01609_amd import rbc as R
+    for name in declared_functions():
+        assert callable(getattr(R, name)), name
+
+
+def test_params_struct_layout_matches_c():
+    """Compile a tiny C program against rbc.h and compare sizeof/offsetof."""
+    from paper_2001_01609_amd import rbc as R
+    fields = [f for f, _ in R.rbc_params._fields_]
+    prog = "#include <stdio.h>\n#include <stddef.h>\n#include \"rbc.h\"\nint main(void){\n"
+    prog += 'printf("%zu\\n", sizeof(rbc_params));\n'
+    for f in fields:
+        prog += f'printf("%zu\\n", offsetof(rbc_params, {f}));\n'
+    prog += "return 0;}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(R.rbc_params)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(R.rbc_params, f).offset == off, f
+
+
+def test_argument_validation_without_device():
+    from paper_2001_01609_amd import rbc as R
+    p = R.rbc_default_params()
+    assert R.rbc_query_footprint(p) > 0
+    bad = [("Nx", 48), ("Nz", 7), ("Nz", 4), ("Nx_c", 128), ("n_slices", 0), ("scheme_f", 3),
+           ("precision", 7), ("dt_f", 0.0), ("t_end", -1.0)]
+    for field, val in bad:
+        q = R.rbc_default_params()
+        setattr(q, field, val)
+        with pytest.raises(R.RbcError) as ei:
+            R.rbc_query_footprint(q)
+        assert ei.value.status == R.RBC_ERR_ARG
+        with pytest.raises(R.RbcError):
+            R.rbc_create(q)
+        assert R.rbc_last_error(None)
+
+
+def test_footprint_scales_with_slices():
+    from paper_2001_01609_amd import rbc as R
+    import rbc_inputs as I
+    a = R.rbc_query_footprint(R.params_from_workload(I.C2))
+    b = R.rbc_query_footprint(R.params_from_workload(I.C2, n_slices=64, t_end=100.0))
+    assert b > 1.8 * a
+    # the large workload stays far below one GPU's 288 GB
+    c = R.rbc_query_footprint(R.params_from_workload(I.C3))
+    assert c < 16e9
