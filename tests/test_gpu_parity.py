@@ -145,3 +145,230 @@ def test_one_fine_step_fp64(Nx, Nz, scheme):
         R().rbc_destroy(h)
     ref = O.Stepper(g).step(X).pack()
     assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("tile", [None, "6"])
+def test_batch_of_slices_many_steps_fp64(tile, monkeypatch):
+    """Three slices with different states, 25 steps; a mode tile of 6 gives
+    a ragged last tile (Mx = 32)."""
+    if tile:
+        monkeypatch.setenv("RBC_MODE_TILE", tile)
+    p = params(64, 24, Ra=2e4, dt=2e-3, scheme=4, S=3)
+    case(f"batch 3 slices 64x24 25 steps tile={tile}")
+    g = grid(p)
+    Xs = [oracle_state(g, sd, 0.3, steps=3) for sd in (1, 2, 3)]
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        V = torch.empty_like(U)
+        R().rbc_fine_step_batch(h, U, V, 3, 25)
+        torch.cuda.synchronize()
+        got = V.cpu().numpy().reshape(3, -1)
+    finally:
+        R().rbc_destroy(h)
+    st = O.Stepper(g)
+    for i, X in enumerate(Xs):
+        assert rel(got[i], st.run(X, 25).pack()) < FP64_TOL, i
+
+
+@pytest.mark.parametrize("scheme", [2, 4])
+def test_mixed_precision_steps_within_bar(scheme):
+    """FP32 transforms/products, FP64 solves: 50 steps within 1e-6 of the
+    FP64 oracle, Nusselt numbers within 1e-4."""
+    p = params(64, 32, Ra=1e5, dt=2e-3, scheme=scheme, mixed=True, S=2)
+    case(f"mixed 64x32 ARS{scheme} 50 steps")
+    g = grid(p)
+    Xs = [oracle_state(g, sd, 0.3, steps=5) for sd in (7, 8)]
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        R().rbc_fine_step_batch(h, U, U, 2, 50)
+        nu = R().rbc_nusselt(h, U, 2)
+        got = U.cpu().numpy().reshape(2, -1)
+    finally:
+        R().rbc_destroy(h)
+    st = O.Stepper(g)
+    for i, X in enumerate(Xs):
+        Y = st.run(X, 50)
+        assert rel(got[i], Y.pack()) < MIXED_TOL
+        nref = np.array(O.nusselt(g, Y))
+        assert np.all(np.abs(nu[i] - nref) / np.abs(nref) < 1e-4)
+
+
+def test_nusselt_matches_oracle():
+    p = params(32, 16, Ra=1e5, dt=2e-3, S=3)
+    case("nusselt 32x16, 3 states")
+    g = grid(p)
+    Xs = [oracle_state(g, sd, 0.5, steps=20) for sd in (1, 2, 3)]
+    Xs[0] = O.conduction_state(g)
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        nu = R().rbc_nusselt(h, U, 3)
+    finally:
+        R().rbc_destroy(h)
+    for i, X in enumerate(Xs):
+        assert np.allclose(nu[i], O.nusselt(g, X), rtol=0, atol=1e-12), (i, nu[i])
+    assert np.allclose(nu[0], 1.0, atol=1e-14)
+
+
+def test_conduction_state_fixed_point_on_gpu():
+    for mixed in (False, True):
+        p = params(32, 16, Ra=1e6, dt=1e-2, mixed=mixed)
+        case(f"conduction fixed point mixed={mixed}")
+        g = grid(p)
+        X = O.conduction_state(g).pack()
+        h = create(p)
+        try:
+            U = to_dev(X)
+            R().rbc_fine_step_batch(h, U, U, 1, 20)
+            nu = R().rbc_nusselt(h, U, 1)[0]
+            got = U.cpu().numpy()
+        finally:
+            R().rbc_destroy(h)
+        assert np.abs(got - X).max() < 1e-15
+        assert np.allclose(nu, 1.0, atol=1e-14)
+
+
+def test_slice_alone_equals_slice_in_batch_bitwise():
+    p = params(32, 16, Ra=1e5, dt=2e-3, S=4, mixed=True)
+    case("batch invariance 4 slices")
+    g = grid(p)
+    Xs = [oracle_state(g, sd, 0.3) for sd in range(4)]
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        R().rbc_fine_step_batch(h, U, U, 4, 30)
+        V = to_dev(Xs[2].pack())
+        R().rbc_fine_step_batch(h, V, V, 1, 30)
+        torch.cuda.synchronize()
+        a = U.cpu().numpy().reshape(4, -1)[2]
+        b = V.cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    assert np.array_equal(a, b)
+
+
+def _tiny_parareal_params(mixed=False):
+    return params(32, 16, Ra=3e3, dt=0.02, scheme=4, mixed=mixed, S=4, Nx_c=16, Nz_c=8, t_end=2.0,
+                  dt_c=0.05)
+
+
+def test_parareal_matches_oracle_iterates():
+    """parareal_iterate vs the oracle's serial Parareal: same iterates (FP64)."""
+    p = _tiny_parareal_params()
+    case("parareal 32x16 / 16x8, 4 slices vs oracle")
+    fine = grid(p)
+    coarse = O.Grid(p.Ra, p.Pr, p.Lx, p.Lz, p.Nx_c, p.Nz_c, p.dt_c, scheme=p.scheme_c)
+    pp = O.RBCParareal(fine, coarse, p.t0, p.t_end, p.n_slices)
+    U0 = O.initial_state(fine, I.gaussian_noise(11, fine.Nx, fine.Nz), 0.3).pack()
+    for k_max in (0, 1, 2):
+        ref = pp.run(U0, k_max=k_max)
+        h = create(p)
+        try:
+            n = R().rbc_state_size(h)
+            U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev())
+            U[:n] = to_dev(U0)
+            st, kd, defects, _ = R().parareal_iterate(h, U, k_max, 0.0)
+            got = U.cpu().numpy().reshape(p.n_slices + 1, -1)
+        finally:
+            R().rbc_destroy(h)
+        assert kd == k_max
+        for nn in range(p.n_slices + 1):
+            assert rel(got[nn], ref.U[nn]) < FP64_TOL, (k_max, nn)
+        assert np.allclose(defects, ref.defects, rtol=1e-8, atol=1e-14)
+
+
+def test_parareal_exact_on_first_k_slices_bitwise():
+    """After k iterations slices 0..k equal the serial fine solve bitwise;
+    at k = S the whole trajectory does (finite termination)."""
+    p = _tiny_parareal_params(mixed=True)
+    case("parareal finite termination, mixed")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(12, g.Nx, g.Nz), 0.3).pack()
+    h = create(p)
+    try:
+        nf, _ = R().rbc_steps_per_slice(h, 0)
+        n = R().rbc_state_size(h)
+        serial = [to_dev(U0)]
+        for s in range(p.n_slices):
+            v = serial[-1].clone()
+            R().rbc_fine_step_batch(h, v, v, 1, nf)
+            serial.append(v)
+        ser = torch.stack(serial).cpu().numpy()
+        for k in range(0, p.n_slices + 1):
+            U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev())
+            U[:n] = serial[0]
+            st, kd, defects, _ = R().parareal_iterate(h, U, k, 0.0)
+            got = U.cpu().numpy().reshape(p.n_slices + 1, -1)
+            for nn in range(k + 1):
+                assert np.array_equal(got[nn], ser[nn]), (k, nn)
+    finally:
+        R().rbc_destroy(h)
+
+
+def test_parareal_reports_nonfinite():
+    p = _tiny_parareal_params()
+    case("parareal non-finite detection")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(13, g.Nx, g.Nz), 0.3).pack()
+    U0[5] = np.nan
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        with pytest.raises(R().RbcError) as ei:
+            R().parareal_iterate(h, U, 2, 0.0)
+        assert ei.value.status == R().RBC_ERR_NONFINITE
+    finally:
+        R().rbc_destroy(h)
+
+
+def test_parareal_stops_at_tolerance_and_tracks_nu():
+    p = _tiny_parareal_params()
+    p.nu_stride = 5
+    p.nu_t_start = 0.5
+    case("parareal tolerance stop + Nu history")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(14, g.Nx, g.Nz), 0.3).pack()
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        st, kd, defects, nu = R().parareal_iterate(h, U, 4, 1e-3, want_nu=True)
+    finally:
+        R().rbc_destroy(h)
+    assert st in (R().RBC_OK, R().RBC_NOT_CONVERGED)
+    if st == R().RBC_OK and kd < p.n_slices:
+        assert defects[-1] <= 1e-3
+    assert np.all(np.isfinite(nu[1:]))
+    # Nu_V, Nu_b, Nu_t of the fine trajectory are near each other and >= 1
+    assert np.all(nu[1:] > 0.99)
+
+
+@pytest.mark.parametrize("w", [I.C2, I.C2_FP64])
+def test_fullsize_batch_sampled_slices(w):
+    """The benchmark's shape (32 slices of 256x64): one batched step, slices
+    0 and 31 checked against the oracle."""
+    p = R().params_from_workload(w)
+    case(f"full size {w.name}: 32 slices, 1 step")
+    g = grid(p)
+    h = create(p)
+    try:
+        nf, dt = R().rbc_steps_per_slice(h, 0)
+        g = grid(p, dt)
+        n = R().rbc_state_size(h)
+        X0 = oracle_state(g, 0, 1e-3)
+        X1 = oracle_state(g, 31, 1e-1)
+        host = np.stack([X0.pack() if s % 2 == 0 else X1.pack() for s in range(p.n_slices)])
+        U = to_dev(host.reshape(-1))
+        R().rbc_fine_step_batch(h, U, U, p.n_slices, 2)
+        got = U.cpu().numpy().reshape(p.n_slices, n)
+    finally:
+        R().rbc_destroy(h)
+    st = O.Stepper(g)
+    tol = MIXED_TOL if w.mixed else FP64_TOL
+    assert rel(got[0], st.run(X0, 2).pack()) < tol
+    assert rel(got[31], st.run(X1, 2).pack()) < tol
