@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the Parareal hot path for 2D Rayleigh-Benard convection on
+one MI355X.
+
+Workload: Ra = 1e6, Pr = 1, aspect ratio 2, fine grid 256 x 64, 32 time
+slices over t in [0, 50], fine step 2e-4 (7813 steps per slice), coarse grid
+128 x 32 at step 2e-3, ARS(4,4,3), mixed precision (FP32 transforms and
+products, FP64 state, solves, correction, defect and Nusselt numbers).
+
+One timed step is one Parareal iteration with every slice active: the fine
+propagator on all 32 slices over their whole slice (with Nusselt samples
+every 50 fine steps), then the serial coarse correction sweep, the
+correction U_{n+1} = G(U_n^new) + F(U_n^old) - G(U_n^old) and the defect.
+`value` is fine DOF-steps (grid points x slices x fine steps) per second of
+the whole iteration's wall time, so the coarse sweep counts against it.
+
+The roofline object describes the dominant kernel (the per-mode stage
+kernel): algorithmic bytes per launch from the byte model below, divided
+by its mean launch duration measured with HIP events on the library's
+stream during the timed steps.  The cpu_baseline object times the FP64
+CPU oracle on one host core over a bounded number of fine steps of one slice.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import rbc_inputs as I  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+NU_STRIDE = 50
+TIMING_EVERY = 97
+
+
+def stage_kernel_bytes_per_dof_step(s: int, rb: int) -> float:
+    """Compulsory HBM bytes of the stage kernel per grid point and slice over
+    one fine step (all s stage launches).  Per launch i = 1..s it reads the
+    two product fields on the padded grid (2 x 1.5 values per point of Real),
+    the old state (2 doubles per point), the i-1 stored explicit terms (Real)
+    and i-1 stored implicit terms (FP64), and writes the explicit term and
+    the implicit term for later stages (i < s), the new state (i = s) and the
+    six padded-grid fields of the next x-pass (6 x 1.5 Real per point)."""
+    tot = 0.0
+    for i in range(1, s + 1):
+        tot += 2 * 1.5 * rb + 2 * 8 + (i - 1) * 2 * rb + (i - 1) * 2 * 8
+        if i < s:
+            tot += 2 * rb + 2 * 8
+        else:
+            tot += 2 * 8
+        tot += 6 * 1.5 * rb
+    return tot
+
+
+def xpass_bytes_per_dof_step(s: int, rb: int) -> float:
+    """x-pass: reads six padded-grid fields and writes two (per stage)."""
+    return s * (6 * 1.5 * rb + 2 * 1.5 * rb)
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per stage-kernel launch from the committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
+    summary is for another workload or the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
+    src = os.path.join(ROOT, "paper_2001_01609_amd", "csrc", "rbc_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        cur = hashlib.sha256(f.read()).hexdigest()[:16]
+    if kv.get("workload") != workload or kv.get("kernel_source_sha256_16") != cur:
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def cpu_baseline(w, seconds: float):
+    """Time the FP64 oracle's fine steps on one slice, one host thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rbc_oracle as O
+    n, dt = O.steps_per_slice(w.t0, w.t_end, w.n_slices, w.dt_f)
+    g = O.Grid(w.Ra, w.Pr, w.Lx, w.Lz, w.Nx, w.Nz, dt, scheme=w.scheme)
+    with threadpool_limits(limits=1):
+        st = O.Stepper(g)
+        X = O.initial_state(g, I.gaussian_noise(w.seed, w.Nx, w.Nz), w.noise_amp)
+        X = st.step(X)
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            X = st.step(X)
+            steps += 1
+        el = time.perf_counter() - t0
+    return {"value": w.Nx * w.Nz * steps / el, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 fine steps of one {w.Nx}x{w.Nz} slice (ARS443, dt {dt:.6g}) "
+                      f"from the seeded initial state; {el:.1f} s on one thread"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=I.C2.name, choices=sorted(I.WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample length (0 = skip)")
+    ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
+                    help="counter-collection mode: only N batched fine steps (same kernels and launch "
+                         "shapes as the timed run), no Parareal iteration, no JSON line")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device-to-device copy of MIB MiB (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the slices of a run would shard "
+              "across GPUs as described in the design notes, but no multi-GPU path is built.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+
+    w = I.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0)
+    h = R.rbc_create(p, stream.cuda_stream)
+    S = w.n_slices
+    try:
+        n = R.rbc_state_size(h, 0)
+        nc = R.rbc_state_size(h, 1)
+        nf, dtf = R.rbc_steps_per_slice(h, 0)
+        ncs, dtc = R.rbc_steps_per_slice(h, 1)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
+        F = torch.zeros(S * n, dtype=torch.float64, device=dev)
+        G = torch.zeros(S * nc, dtype=torch.float64, device=dev)
+        nu = torch.zeros(S * (nf // NU_STRIDE) * 3, dtype=torch.float64, device=dev)
+        R.rbc_init_state(h, w.seed, w.noise_amp, U)
+        # realistic slice-start states: the coarse prediction (untimed)
+        R.rbc_coarse_sweep(h, 0, 0, U, None, G)
+        torch.cuda.synchronize()
+
+        def iteration():
+            R.rbc_fine_step_batch(h, U, F, S, nf, nu)
+            return R.rbc_coarse_sweep(h, 1, 0, U, F, G, want_defect=True)
+
+        def calibrate():
+            if args.calibrate_copy > 0:
+                a = torch.empty(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
+                b = torch.empty_like(a)
+                b.copy_(a)
+                torch.cuda.synchronize()
+                del a, b
+
+        if args.profile_steps > 0:
+            R.rbc_fine_step_batch(h, U, F, S, args.profile_steps, None)
+            torch.cuda.synchronize()
+            calibrate()
+            print(f"[bench] profile mode: {args.profile_steps} batched fine steps done", file=sys.stderr)
+            return 0
+
+        for it in range(args.warmup):
+            iteration()
+            torch.cuda.synchronize()
+            print(f"[bench] warmup iteration {it + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        R.rbc_kernel_timing_enable(h, 0, TIMING_EVERY)
+        defects = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(args.steps):
+            defects.append(iteration())
+            print(f"[bench] timed iteration {it + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        k_ms, k_cnt = R.rbc_kernel_timing(h)
+        R.rbc_kernel_timing_enable(h, -1, 0)
+        # fine propagator alone (events around one batched F call)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        R.rbc_fine_step_batch(h, U, F, S, nf, nu)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        f_ms = e0.elapsed_time(e1)
+        calibrate()
+        nu_host = nu.view(S, -1, 3).cpu().numpy()
+        finite = bool(np.isfinite(U.cpu().numpy()).all())
+    finally:
+        R.rbc_destroy(h)
+
+    dof = w.Nx * w.Nz
+    fine_dof_steps = dof * S * nf
+    ms_step = 1e3 * el / args.steps
+    value = fine_dof_steps * args.steps / el
+    rb = 4 if w.mixed else 8
+    s = w.scheme
+    per_launch = stage_kernel_bytes_per_dof_step(s, rb) / s * dof * S
+    achieved = per_launch / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    traffic = measured_traffic(w.name)
+    out = {
+        "metric": "fine-step DOF-steps/s (%HBM roofline); Parareal vs serial time-to-solution",
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if w.mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "Ra": w.Ra, "Pr": w.Pr, "grid": [w.Nx, w.Nz],
+                   "coarse_grid": [w.Nx_c, w.Nz_c], "slices": S, "t": [w.t0, w.t_end],
+                   "fine_steps_per_slice": nf, "coarse_steps_per_slice": ncs, "scheme": "ARS443" if s == 4 else "ARS222",
+                   "step": "one Parareal iteration, all slices active"},
+        "roofline": {"bound": "hbm", "kernel": "stage_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": per_launch, "mean_launch_ms": k_ms, "timed_launches": k_cnt},
+        "fine_propagator": {"dof_steps_per_s": fine_dof_steps / (f_ms * 1e-3), "ms_per_call": f_ms,
+                            "us_per_batched_step": 1e3 * f_ms / nf,
+                            "bytes_per_dof_step_model": stage_kernel_bytes_per_dof_step(s, rb) +
+                            xpass_bytes_per_dof_step(s, rb)},
+        "parareal": {"defects": defects, "nu_mean_last": [float(v) for v in nu_host.reshape(-1, 3).mean(0)],
+                     "finite": finite},
+    }
+    if args.cpu_seconds > 0:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        cb = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -26,6 +26,7 @@ struct rbc_ctx {
   double* nu_f = nullptr;      // [S][nsf][3]
   double* nu_c = nullptr;      // [S][nsc][3]
   int nsf = 0, nsc = 0, stride_c = 0;
+  rbc::KernelTiming timing;    // fine-grid kernel timing (rbc_kernel_timing_*)
   std::string err;
 };
 
@@ -88,13 +89,14 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.T_bot = p->T_bot; g.T_top = p->T_top;
   g.scheme = coarse ? p->scheme_c : p->scheme_f;
   g.mixed = (p->precision == RBC_MIXED);
-  g.MT = (g.Nz >= 128) ? 4 : 8;
-  // modes per block of the per-mode kernel; RBC_MODE_TILE overrides (1..32)
+  // modes per block of the per-mode kernel (2, 4, 6 or 8); RBC_MODE_TILE overrides
+  // (the single-slice coarse grid is latency-bound: small tiles, more blocks)
+  g.MT = (coarse || g.Nz >= 128) ? 2 : 4;
   if (const char* e = std::getenv("RBC_MODE_TILE")) {
     const int v = std::atoi(e);
-    if (v >= 1 && v <= 32) g.MT = v;
+    if (v == 2 || v == 4 || v == 6 || v == 8) g.MT = v;
   }
-  if (g.MT > g.Mx) g.MT = g.Mx;
+  if (g.MT > g.Mx) g.MT = g.Mx;   // Mx is a power of two >= 2
 }
 
 size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::GridPlan& c, int nsf, int nsc) {
@@ -110,6 +112,8 @@ size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::Gri
 
 void release(rbc_handle h) {
   if (!h) return;
+  for (hipEvent_t e : h->timing.ev) (void)hipEventDestroy(e);
+  h->timing.ev.clear();
   rbc::free_work(h->wf);
   rbc::free_work(h->wc);
   for (void* q : {(void*)h->Xc, (void*)h->Fbuf, (void*)h->Gbuf, (void*)h->part, (void*)h->dscal,
@@ -313,7 +317,7 @@ rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in, double* U_out, 
   const int stride = h->p.nu_stride;
   const int ld = (nu_samples && stride > 0) ? n_steps / stride : 0;
   HIPCHK(h, rbc::launch_steps(h->fine, h->wf, U_out, n_slices, n_steps, ld > 0 ? nu_samples : nullptr, stride,
-                              ld, h->stream));
+                              ld, h->stream, &h->timing));
   return RBC_OK;
 }
 
@@ -410,7 +414,7 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
     HIPCHK(h, hipMemcpyAsync(h->Fbuf + (k - 1) * fs, U + (k - 1) * fs, size_t(na) * fs * 8,
                              hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, rbc::launch_steps(h->fine, h->wf, h->Fbuf + (k - 1) * fs, na, h->nf, nu, h->p.nu_stride, h->nsf,
-                                h->stream));
+                                h->stream, &h->timing));
     // U_k^k = F(U_(k-1)^(k-1)) exactly; then the correction sweep
     HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, 2, U + k * fs, h->Fbuf + (k - 1) * fs, nullptr, nullptr,
                                   h->part + size_t(k) * rbc::kCombineBlocks * 2, h->stream));
@@ -446,6 +450,33 @@ rbc_status rbc_explicit_terms(rbc_handle h, const double* U, double* E) {
   if (!h || !U || !E) return fail(h, RBC_ERR_ARG, "null argument");
   HIPCHK(h, hipMemsetAsync(E, 0, size_t(h->fine.dev.state) * 8, h->stream));
   HIPCHK(h, rbc::launch_explicit(h->fine, h->wf, U, E, h->stream));
+  return RBC_OK;
+}
+
+rbc_status rbc_kernel_timing_enable(rbc_handle h, int32_t kernel, int32_t every) {
+  if (!h) return RBC_ERR_ARG;
+  if (kernel < -1 || kernel > 1 || every < 0) return fail(h, RBC_ERR_ARG, "kernel must be -1, 0 or 1; every >= 0");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->timing.kernel = kernel;
+  h->timing.every = (kernel < 0) ? 0 : every;
+  h->timing.used = 0;
+  return RBC_OK;
+}
+
+rbc_status rbc_kernel_timing(rbc_handle h, double* mean_ms, int64_t* count) {
+  if (!h || !mean_ms || !count) return fail(h, RBC_ERR_ARG, "null argument");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double tot = 0;
+  int64_t n = 0;
+  for (size_t i = 0; i + 1 < h->timing.used; i += 2) {
+    float ms = 0;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->timing.ev[i], h->timing.ev[i + 1]));
+    tot += ms;
+    ++n;
+  }
+  *mean_ms = n ? tot / n : 0.0;
+  *count = n;
+  h->timing.used = 0;
   return RBC_OK;
 }
 

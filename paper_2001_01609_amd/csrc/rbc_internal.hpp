@@ -25,7 +25,7 @@ namespace rbc {
 constexpr int kMaxStages = 5;     // s + 1 stages of ARS(4,4,3)
 constexpr int kBlock = 256;       // threads per block of the per-mode kernels
 
-// Per-row entries of the stored factorisations (see build_factors()).
+// Per-row entries of the stored bordered band factorisations (rbc_plan.cpp).
 constexpr int kFacT = 4;          // lm, 1/u_ii, u_i,i+1, v      (bordered tridiagonal)
 constexpr int kFacP = 7;          // lm1, lm2, 1/u_ii, u1, u2, v0, v1 (bordered pentadiagonal)
 
@@ -98,12 +98,24 @@ size_t work_bytes(const GridPlan& g, int cap);
 hipError_t alloc_work(const GridPlan& g, int cap, Work& w);
 void free_work(Work& w);
 
+// HIP-event timing of one kernel of the fine propagator: on every `every`-th
+// step each launch of `kernel` (0 = stage kernel, 1 = x-pass) is bracketed by
+// an event pair on the launch stream.
+struct KernelTiming {
+  int kernel = -1;
+  int every = 0;
+  std::vector<hipEvent_t> ev;   // pairs: start, stop
+  size_t used = 0;              // events in use
+  static constexpr size_t kMaxPairs = 8192;
+};
+
 // ---- launchers (rbc_kernels.hip) -----------------------------------------
 // Advance n_slices contiguous states X in place by n_steps IMEX steps.  If
 // nu_out is not null, after every nu_stride-th step the Nusselt numbers of each
 // slice go to nu_out[s * nu_ld + sample][3].
 hipError_t launch_steps(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps,
-                        double* nu_out, int nu_stride, int nu_ld, hipStream_t st);
+                        double* nu_out, int nu_stride, int nu_ld, hipStream_t st,
+                        KernelTiming* timing = nullptr);
 // Explicit terms of one state (diagnostic): E = state-shaped FP64 array.
 hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st);
 // Nusselt numbers of n states: out[i*ld3 .. +3] (ld3 = stride in doubles).
@@ -122,8 +134,5 @@ hipError_t launch_combine(const GridPlan& f, const GridPlan& c, int mode, double
 // Reduce partials of slices [first, last) (part is [S+1][kCombineBlocks][2]) into
 // out[0] = max relative defect, out[1] = non-finite flag (0/1).
 hipError_t launch_defect(const double* part, int first, int last, double* out, hipStream_t st);
-// Mean of Nu samples (n_rows rows of 3 doubles, rows in [row0, n_rows) used) -> out[3].
-hipError_t launch_nu_mean(const double* samples, int n_rows, const int* use, double* out,
-                          hipStream_t st);
 
 }  // namespace rbc

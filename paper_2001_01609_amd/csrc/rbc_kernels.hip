@@ -122,9 +122,11 @@ __global__ void __launch_bounds__(kBlock) xpass_kernel(GridDev g, const Real* __
   const int s = blockIdx.x / Pz, j = blockIdx.x - s * Pz;
   Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem);   // [3][Px]
   Cx<Real>* B = A + 3 * Px;                           // [3][Px]
-  Real* red = reinterpret_cast<Real*>(B + 3 * Px);    // [blockDim]
-  const Cx<Real>* tw = reinterpret_cast<const Cx<Real>*>(g.tw);
+  Cx<Real>* tw = B + 3 * Px;                          // [Px] twiddles
+  Real* red = reinterpret_cast<Real*>(tw + Px);       // [blockDim]
+  const Cx<Real>* gtw = reinterpret_cast<const Cx<Real>*>(g.tw);
 
+  for (int t = threadIdx.x; t < Px; t += blockDim.x) tw[t] = gtw[t];
   for (int t = threadIdx.x; t < 3 * Px; t += blockDim.x) A[t] = {Real(0), Real(0)};
   __syncthreads();
   // pack (u, w), (omega_x, omega_z), (T_x, T_z) into three complex spectra
@@ -183,34 +185,39 @@ struct StageArgs {
   double haii;
 };
 
-__device__ __forceinline__ int ldv(const GridDev& g) { return g.Nz + 1; }
+// LDS strides (in doubles) of one staged factor block: odd, so that lanes
+// reading different blocks at the same row fall in different banks.
+__host__ __device__ __forceinline__ int lds_fac_stride(int s) { return s | 1; }
 
 // Bordered tridiagonal solve in place on v[2 i + p] (stride-2 view of one
-// parity): temperature and mean-flow systems.
-__device__ void solve_T_format(double* v, int p, const double* __restrict__ fac, int nr, double gbc) {
-  // forward: y_i = f_i - l_i y_(i-1)
+// parity): temperature and mean-flow systems.  fac: kFacT per row, then the
+// 1 x 1 Schur inverse.
+__device__ __forceinline__ void solve_T_format(double* v, int p, const double* fac, int nr, double gbc) {
   double y = v[p];
+#pragma unroll 4
   for (int i = 1; i < nr; ++i) {
     y = v[2 * i + p] - fac[i * kFacT + 0] * y;
     v[2 * i + p] = y;
   }
-  // backward: x_i = (y_i - u_i x_(i+1)) / d_i, with s = sum x_i
   double x = v[2 * (nr - 1) + p] * fac[(nr - 1) * kFacT + 1];
   v[2 * (nr - 1) + p] = x;
   double sum = x;
+#pragma unroll 4
   for (int i = nr - 2; i >= 0; --i) {
     x = (v[2 * i + p] - fac[i * kFacT + 2] * x) * fac[i * kFacT + 1];
     v[2 * i + p] = x;
     sum += x;
   }
   const double xh = fac[nr * kFacT] * (gbc - sum);
+#pragma unroll 4
   for (int i = nr - 1; i >= 0; --i) v[2 * (i + 1) + p] = v[2 * i + p] - fac[i * kFacT + 3] * xh;
   v[p] = xh;
 }
 
 // Bordered pentadiagonal solve in place (streamfunction, two border unknowns).
-__device__ void solve_P_format(double* v, int p, const double* __restrict__ fac, int nr) {
+__device__ __forceinline__ void solve_P_format(double* v, int p, const double* fac, int nr) {
   double y2 = 0, y1 = 0;
+#pragma unroll 4
   for (int i = 0; i < nr; ++i) {
     const double y = v[2 * i + p] - fac[i * kFacP + 0] * y1 - fac[i * kFacP + 1] * y2;
     v[2 * i + p] = y;
@@ -218,6 +225,7 @@ __device__ void solve_P_format(double* v, int p, const double* __restrict__ fac,
     y1 = y;
   }
   double x1 = 0, x2 = 0, s0 = 0, s1 = 0;
+#pragma unroll 4
   for (int i = nr - 1; i >= 0; --i) {
     const double* f = fac + i * kFacP;
     const double x = (v[2 * i + p] - f[3] * x1 - f[4] * x2) * f[2];
@@ -231,27 +239,45 @@ __device__ void solve_P_format(double* v, int p, const double* __restrict__ fac,
   const double* si = fac + nr * kFacP;
   const double h0 = -(si[0] * s0 + si[1] * s1);
   const double h1 = -(si[2] * s0 + si[3] * s1);
+#pragma unroll 4
   for (int i = nr - 1; i >= 0; --i)
     v[2 * (i + 2) + p] = v[2 * i + p] - fac[i * kFacP + 5] * h0 - fac[i * kFacP + 6] * h1;
   v[p] = h0;
   v[2 + p] = h1;
 }
 
-template <typename Real>
+// Copies the factor blocks of modes m0..m0+MT-1 (both parities) into LDS.
+template <int MT>
+__device__ __forceinline__ void stage_factors(double* sF, const double* __restrict__ fac, int stride, int m0,
+                                              int Mx) {
+  const int ls = lds_fac_stride(stride);
+  const int nm = min(MT, Mx - m0);
+  const double* src = fac + size_t(m0) * 2 * stride;
+  for (int e = threadIdx.x; e < nm * 2 * stride; e += blockDim.x) {
+    const int b = e / stride, o = e - b * stride;
+    sF[b * ls + o] = src[e];
+  }
+}
+
+// LDS layout of a block (doubles first, then Real):
+//   sY  double [2 field][MT][2 re/im][Nz+1]     right-hand sides -> new stage
+//   U   union { Real sN[2][Pz][MT][2] + sq[Pz];  double sF[MT*2][odd stride] }
+template <typename Real, int MT>
 __global__ void __launch_bounds__(kBlock)
 stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __restrict__ qbar,
              double* __restrict__ X, Real* __restrict__ Ehist, double* __restrict__ LYhist,
              Real* __restrict__ Q, double* __restrict__ Eout) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int Nz = g.Nz, Mx = g.Mx, Pz = g.Pz, Ph = Pz / 2, MT = g.MT, LD = ldv(g);
+  const int Nz = g.Nz, Mx = g.Mx, Pz = g.Pz, Ph = Pz / 2, LD = Nz + 1;
   const int ntile = (Mx + MT - 1) / MT;
   const int s = blockIdx.x / ntile, tile = blockIdx.x - s * ntile;
   const int m0 = tile * MT;
   const int st = g.state;
-  double* sY = reinterpret_cast<double*>(smem);       // [2][MT][2][LD]
-  double* sX = sY + 4 * MT * LD;                       // [2][MT][2][LD]
-  Real* sN = reinterpret_cast<Real*>(sX + 4 * MT * LD);  // [2][Pz][MT][2]
-  Real* sq = sN + 4 * Pz * MT;                         // [Pz]
+  double* sY = reinterpret_cast<double*>(smem);
+  unsigned char* uni = smem + sizeof(double) * 4 * MT * LD;
+  Real* sN = reinterpret_cast<Real*>(uni);
+  Real* sq = sN + 4 * Pz * MT;
+  double* sF = reinterpret_cast<double*>(uni);
   auto yi = [&](int f, int mt, int ri) { return ((f * MT + mt) * 2 + ri) * LD; };
   auto gidx = [&](int f, int m, int ri) { return size_t(((f * Mx + m) * 2 + ri)) * Nz; };
   const double* Xs = X + size_t(s) * st;
@@ -265,71 +291,100 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     }
     __syncthreads();
   } else {
-    // ---- phase A: products of this tile and the old state
+    // ---- phase A: products of this tile on the padded Gauss points
+    // (8 loads in flight per thread before the LDS stores)
     const size_t rowQ = size_t(Mx) * 2;
-    for (int e = tid; e < 4 * Pz * MT; e += nth) {
-      const int c = e % (2 * MT), j = (e / (2 * MT)) % Pz, qq = e / (2 * MT * Pz);
-      const int m = m0 + (c >> 1);
-      sN[e] = (m < Mx) ? Nh[((size_t(s) * 2 + qq) * Pz + j) * rowQ + 2 * m0 + c] : Real(0);
+    {
+      constexpr int U = 8;
+      const int total = 4 * Pz * MT;
+      for (int base = tid; base < total; base += nth * U) {
+        Real v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = base + u * nth;
+          v[u] = Real(0);
+          if (e < total) {
+            const int c = e % (2 * MT), j = (e / (2 * MT)) % Pz, qq = e / (2 * MT * Pz);
+            if (m0 + (c >> 1) < Mx) v[u] = Nh[((size_t(s) * 2 + qq) * Pz + j) * rowQ + 2 * m0 + c];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = base + u * nth;
+          if (e < total) sN[e] = v[u];
+        }
+      }
     }
     if (m0 == 0)
       for (int j = tid; j < Pz; j += nth) sq[j] = qbar[size_t(s) * Pz + j];
-    if (a.mode == kModeStage)
-      for (int e = tid; e < 4 * MT * Nz; e += nth) {
-        const int nn = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
-        const int m = m0 + mt;
-        sX[yi(f, mt, ri) + nn] = (m < Mx) ? Xs[gidx(f, m, ri) + nn] : 0.0;
-      }
     __syncthreads();
-    // ---- phase B: explicit terms of the previous stage, band rows only
+    // ---- phase B: explicit terms of the previous stage on the band rows.
+    // Item (f, r): one row of the folded forward map against every column
+    // (mode, re/im) of the tile; the u_bar column of mode 0 separately.
     const Real* W = reinterpret_cast<const Real*>(g.Wfwd);
-    for (int e = tid; e < 4 * MT * Nz; e += nth) {
-      const int r = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
-      const int m = m0 + mt;
-      if (m >= Mx) continue;
-      double E = 0.0;
-      const int rows = (f == 0 && m > 0) ? Nz - 4 : Nz - 2;
-      if (r < rows) {
-        const Real* w;
-        const Real* src;
-        int sstride;
-        Real sgn;
-        if (f == 1) {
-          w = W + (size_t(1) * Nz + r) * Ph;
-          src = sN + (Pz + 0) * 2 * MT + 2 * mt + ri;   // N_T block
-          sstride = 2 * MT;
-          sgn = (r & 1) ? Real(-1) : Real(1);
-        } else if (m > 0) {
-          w = W + (size_t(0) * Nz + r) * Ph;
-          src = sN + 2 * mt + ri;                         // N_omega block
-          sstride = 2 * MT;
-          sgn = (r & 1) ? Real(-1) : Real(1);
-        } else {
-          w = W + (size_t(2) * Nz + r) * Ph;
-          src = sq;
-          sstride = 1;
-          sgn = (r & 1) ? Real(1) : Real(-1);
-        }
-        if (f == 0 && m == 0 && ri == 1) {
-          E = 0.0;
-        } else {
+    const int nitems = 2 * Nz + (m0 == 0 ? Nz : 0);
+    for (int e = tid; e < nitems; e += nth) {
+      const int r = e % Nz, f = e / Nz;   // f = 2: the u_bar column
+      const int rows = (f == 0) ? Nz - 4 : Nz - 2;
+      if (f == 2) {
+        double E = 0.0;
+        if (r < Nz - 2) {
+          const Real* w = W + (size_t(2) * Nz + r) * Ph;
+          const Real sg = (r & 1) ? Real(1) : Real(-1);
           Real acc = 0;
-          for (int j = 0; j < Ph; ++j)
-            acc += w[j] * (src[j * sstride] + sgn * src[(Pz - 1 - j) * sstride]);
+#pragma unroll 8
+          for (int j = 0; j < Ph; ++j) acc += w[j] * (sq[j] + sg * sq[Pz - 1 - j]);
           E = double(acc);
         }
+        if (a.mode == kModeExplicit) {
+          Eout[gidx(0, 0, 0) + r] = E;
+          Eout[gidx(0, 0, 1) + r] = 0.0;
+        } else {
+          sY[yi(0, 0, 0) + r] = a.hae[a.stage - 1] * E;
+          sY[yi(0, 0, 1) + r] = 0.0;
+          if (a.store_E) {
+            Real* eh = Ehist + (size_t(a.stage - 1) * a.cap + s) * st;
+            eh[gidx(0, 0, 0) + r] = Real(E);
+            eh[gidx(0, 0, 1) + r] = Real(0);
+          }
+        }
+        continue;
       }
-      if (a.mode == kModeExplicit) {
-        Eout[gidx(f, m, ri) + r] = E;
-      } else {
-        sY[yi(f, mt, ri) + r] = a.hae[a.stage - 1] * E;
-        if (a.store_E)
-          Ehist[(size_t(a.stage - 1) * a.cap + s) * st + gidx(f, m, ri) + r] = Real(E);
+      Real acc[2 * MT];
+#pragma unroll
+      for (int c = 0; c < 2 * MT; ++c) acc[c] = Real(0);
+      if (r < rows) {
+        const Real* w = W + (size_t(f == 0 ? 0 : 1) * Nz + r) * Ph;
+        const Real* src = sN + (f == 0 ? 0 : Pz * 2 * MT);
+        const Real sg = (r & 1) ? Real(-1) : Real(1);
+#pragma unroll 8
+        for (int j = 0; j < Ph; ++j) {
+          const Real wv = w[j];
+          const Real* a0 = src + j * 2 * MT;
+          const Real* a1 = src + (Pz - 1 - j) * 2 * MT;
+#pragma unroll
+          for (int c = 0; c < 2 * MT; ++c) acc[c] += wv * (a0[c] + sg * a1[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 2 * MT; ++c) {
+        const int mt = c >> 1, ri = c & 1, m = m0 + mt;
+        if (m >= Mx || (f == 0 && m == 0)) continue;
+        const double E = double(acc[c]);
+        if (a.mode == kModeExplicit) {
+          Eout[gidx(f, m, ri) + r] = E;
+        } else {
+          sY[yi(f, mt, ri) + r] = a.hae[a.stage - 1] * E;
+          if (a.store_E) Ehist[(size_t(a.stage - 1) * a.cap + s) * st + gidx(f, m, ri) + r] = Real(E);
+        }
       }
     }
     if (a.mode == kModeExplicit) return;
     __syncthreads();
+    // temperature factors into the (now free) union region
+    stage_factors<MT>(sF, g.facT, g.facT_stride, m0, Mx);
     // ---- phase C: right-hand side of stage i on the band rows
+#pragma unroll 4
     for (int e = tid; e < 4 * MT * Nz; e += nth) {
       const int r = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
       const int m = m0 + mt;
@@ -338,7 +393,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       const int rows = psi ? Nz - 4 : Nz - 2;
       if (r >= rows) continue;
       const int p = r & 1, i = r >> 1;
-      const double* xv = sX + yi(f, mt, ri);
+      const double* xv = Xs + gidx(f, m, ri);
       double MX = 0;
       if (!psi) {
         const double* b = g.bS10 + (p * g.n + i) * 3;
@@ -370,11 +425,12 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       if (m < Mx) {
         double gbc = 0.0;
         if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
-        solve_T_format(sY + yi(1, mt, ri), p, g.facT + (size_t(m) * 2 + p) * g.facT_stride, g.nrT, gbc);
+        solve_T_format(sY + yi(1, mt, ri), p, sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), g.nrT, gbc);
       }
     }
     __syncthreads();
-    // ---- phase E: implicit buoyancy of the new temperature, then psi / u_bar
+    // flow factors; implicit buoyancy of the new temperature into psi
+    stage_factors<MT>(sF, g.facP, g.facP_stride, m0, Mx);
     for (int e = tid; e < 2 * MT * Nz; e += nth) {
       const int r = e % Nz, c = e / Nz, ri = c & 1, mt = c >> 1, m = m0 + mt;
       if (m >= Mx || m == 0 || r >= Nz - 4) continue;
@@ -391,7 +447,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     if (tid < 4 * MT) {
       const int mt = tid >> 2, p = (tid >> 1) & 1, ri = tid & 1, m = m0 + mt;
       if (m < Mx) {
-        const double* fac = g.facP + (size_t(m) * 2 + p) * g.facP_stride;
+        const double* fac = sF + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
         if (m == 0)
           solve_T_format(sY + yi(0, mt, ri), p, fac, g.nrT, 0.0);
         else
@@ -468,6 +524,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     const Real* w1 = Wi + (size_t(1) * Ph + j) * Nz;
     const Real* w2 = Wi + (size_t(2) * Ph + j) * Nz;
     const Real* w3 = Wi + (size_t(3) * Ph + j) * Nz;
+#pragma unroll 4
     for (int nn = 0; nn < Nz; nn += 2) {
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp) {
@@ -652,21 +709,37 @@ __global__ void defect_kernel(const double* __restrict__ part, int first, int la
 namespace {
 
 size_t stage_lds(const GridDev& d, size_t rb) {
-  return size_t(8) * 4 * d.MT * (d.Nz + 1) * 2 + rb * (4 * size_t(d.Pz) * d.MT + d.Pz);
+  const size_t y = sizeof(double) * 4 * d.MT * (d.Nz + 1);
+  const size_t n = rb * (4 * size_t(d.Pz) * d.MT + d.Pz);
+  const int fs = d.facT_stride > d.facP_stride ? d.facT_stride : d.facP_stride;
+  const size_t f = sizeof(double) * size_t(d.MT) * 2 * lds_fac_stride(fs);
+  return y + (n > f ? n : f);
 }
 size_t xpass_lds(const GridDev& d, size_t rb) {
-  return rb * 2 * (6 * size_t(d.Px)) + rb * kBlock;
+  return rb * 2 * (7 * size_t(d.Px)) + rb * kBlock;
+}
+
+template <typename Real, int MT>
+hipError_t run_stage_mt(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
+                        hipStream_t st) {
+  const GridDev& d = g.dev;
+  const int ntile = (d.Mx + MT - 1) / MT;
+  hipLaunchKernelGGL((stage_kernel<Real, MT>), dim3(n_slices * ntile), dim3(kBlock), stage_lds(d, sizeof(Real)),
+                     st, d, a, (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q,
+                     Eout);
+  return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t run_stage(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices,
-                     double* Eout, hipStream_t st) {
-  const GridDev& d = g.dev;
-  const int ntile = (d.Mx + d.MT - 1) / d.MT;
-  hipLaunchKernelGGL(stage_kernel<Real>, dim3(n_slices * ntile), dim3(kBlock), stage_lds(d, sizeof(Real)),
-                     st, d, a, (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist,
-                     (Real*)w.Q, Eout);
-  return hipGetLastError();
+hipError_t run_stage(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
+                     hipStream_t st) {
+  switch (g.dev.MT) {
+    case 2: return run_stage_mt<Real, 2>(g, w, a, X, n_slices, Eout, st);
+    case 4: return run_stage_mt<Real, 4>(g, w, a, X, n_slices, Eout, st);
+    case 6: return run_stage_mt<Real, 6>(g, w, a, X, n_slices, Eout, st);
+    case 8: return run_stage_mt<Real, 8>(g, w, a, X, n_slices, Eout, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename Real>
@@ -677,9 +750,20 @@ hipError_t run_xpass(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Records an event of the timing pool (start or stop of one launch).
+hipError_t timing_mark(KernelTiming* t, hipStream_t st) {
+  if (t->used >= t->ev.size()) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    t->ev.push_back(e);
+  }
+  return hipEventRecord(t->ev[t->used++], st);
+}
+
 template <typename Real>
 hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps, double* nu_out,
-                      int nu_stride, int nu_ld, hipStream_t st) {
+                      int nu_stride, int nu_ld, hipStream_t st, KernelTiming* tm) {
   if (n_steps <= 0) return hipSuccess;
   const Tableau& tb = g.tab;
   StageArgs a{};
@@ -692,8 +776,12 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n
   int sample = 0;
   for (int step = 0; step < n_steps; ++step) {
     const bool last = (step == n_steps - 1);
+    const bool timed = tm && tm->every > 0 && step % tm->every == 0 &&
+                       tm->used + 2 * tb.s <= 2 * KernelTiming::kMaxPairs;
     for (int i = 1; i <= tb.s; ++i) {
+      if (timed && tm->kernel == 1 && (e = timing_mark(tm, st)) != hipSuccess) return e;
       if ((e = run_xpass<Real>(g, w, n_slices, st)) != hipSuccess) return e;
+      if (timed && tm->kernel == 1 && (e = timing_mark(tm, st)) != hipSuccess) return e;
       StageArgs b{};
       b.mode = kModeStage;
       b.stage = i;
@@ -706,7 +794,9 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n
       for (int j = 0; j < i; ++j) b.hae[j] = g.dt * tb.ae[i][j];
       for (int j = 1; j <= i; ++j) b.hai[j] = g.dt * tb.ai[i][j];
       b.haii = g.dt * tb.ai[i][i];
+      if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
       if ((e = run_stage<Real>(g, w, b, X, n_slices, nullptr, st)) != hipSuccess) return e;
+      if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
     }
     if (nu_out && nu_stride > 0 && (step + 1) % nu_stride == 0) {
       hipLaunchKernelGGL(nusselt_kernel, dim3(n_slices), dim3(kBlock), 0, st, g.dev, X,
@@ -721,9 +811,9 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n
 }  // namespace
 
 hipError_t launch_steps(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps, double* nu_out,
-                        int nu_stride, int nu_ld, hipStream_t st) {
-  if (g.mixed) return steps_impl<float>(g, w, X, n_slices, n_steps, nu_out, nu_stride, nu_ld, st);
-  return steps_impl<double>(g, w, X, n_slices, n_steps, nu_out, nu_stride, nu_ld, st);
+                        int nu_stride, int nu_ld, hipStream_t st, KernelTiming* tm) {
+  if (g.mixed) return steps_impl<float>(g, w, X, n_slices, n_steps, nu_out, nu_stride, nu_ld, st, tm);
+  return steps_impl<double>(g, w, X, n_slices, n_steps, nu_out, nu_stride, nu_ld, st, tm);
 }
 
 hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st) {

@@ -72,6 +72,8 @@ def _load():
         "parareal_iterate": (st, [vp, vp, i32, dbl, P(i32), P(dbl), P(dbl)]),
         "rbc_nusselt": (st, [vp, vp, i32, P(dbl)]),
         "rbc_explicit_terms": (st, [vp, vp, vp]),
+        "rbc_kernel_timing_enable": (st, [vp, i32, i32]),
+        "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64)]),
         "rbc_synchronize": (st, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -176,6 +178,16 @@ def rbc_nusselt(h, U, n_states: int) -> np.ndarray:
 
 def rbc_explicit_terms(h, U, E) -> None:
     _check(_lib.rbc_explicit_terms(h, _ptr(U), _ptr(E)), h)
+
+
+def rbc_kernel_timing_enable(h, kernel: int, every: int) -> None:
+    _check(_lib.rbc_kernel_timing_enable(h, kernel, every), h)
+
+
+def rbc_kernel_timing(h) -> Tuple[float, int]:
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.rbc_kernel_timing(h, ctypes.byref(ms), ctypes.byref(n)), h)
+    return ms.value, n.value
 
 
 def rbc_synchronize(h) -> None:

@@ -465,3 +465,21 @@ def test_steps_per_slice_rounding():
     assert n == 7813 and abs(dt - 1.5625 / 7813) < 1e-18
     n, dt = O.steps_per_slice(0.0, 10.0, 4, 1e-3)
     assert n == 2500 and dt == 1e-3
+
+
+def test_kinetic_energy_closed_form():
+    """psi = b sin(kx) z^2(1-z)^2 and u_bar = c sin(pi z):
+    KE = <(u^2 + w^2)/2> = b^2/4 (int g'^2 + k^2 int g^2) + c^2/4, g = z^2 (1-z)^2."""
+    b, c = 0.07, 0.03
+    g_ = O.Grid(1e5, 1.0, 2.0, 1.0, 16, 32, 1.0)
+    k = g_.k[1]
+    x, z = O.grid_points(g_)
+    psi = b * np.sin(k * x)[:, None] * (z * z * (1 - z) ** 2)[None, :]
+    X = O.State(np.zeros((g_.Mx, g_.Nz), complex), O.from_grid(psi, g_.Mx, g_.Nz))
+    X.P[0] = _cheb_of(lambda s: c * np.sin(np.pi * s), g_.Lz, g_.Nz)
+    gfun = lambda s: s * s * (1 - s) ** 2
+    dg = lambda s: 2 * s * (1 - s) ** 2 - 2 * s * s * (1 - s)
+    I1, _ = scipy.integrate.quad(lambda s: dg(s) ** 2, 0, 1, epsabs=1e-15)
+    I2, _ = scipy.integrate.quad(lambda s: gfun(s) ** 2, 0, 1, epsabs=1e-15)
+    want = b * b / 4 * (I1 + k * k * I2) + c * c / 4
+    assert abs(O.kinetic_energy(g_, X) - want) < 1e-13
