@@ -64,8 +64,11 @@ std::string check_params(const rbc_params* p) {
   if (!(p->Ra > 0) || !(p->Pr > 0) || !(p->Lx > 0) || !(p->Lz > 0)) return "Ra, Pr, Lx, Lz must be > 0";
   if (!pow2(p->Nx) || p->Nx < 4 || !pow2(p->Nx_c) || p->Nx_c < 4)
     return "Nx and Nx_c must be powers of two >= 4 (padded grid 3 Nx / 2)";
-  if (p->Nz < 8 || p->Nz % 2 || p->Nz_c < 8 || p->Nz_c % 2) return "Nz and Nz_c must be even and >= 8";
-  if (p->Nz > 512 || p->Nx > 8192) return "grid too large (Nz <= 512, Nx <= 8192)";
+  if (!pow2(p->Nz) || p->Nz < 8 || p->Nz > 256 || !pow2(p->Nz_c) || p->Nz_c < 8)
+    return "Nz and Nz_c must be powers of two in [8, 256]";
+  // the x-pass keeps seven padded rows of complex values in LDS (160 KiB)
+  if (p->Nx > (p->precision == RBC_MIXED ? 1024 : 512))
+    return "Nx too large for the x-pass LDS (<= 1024 mixed, <= 512 FP64)";
   if (p->Nx_c > p->Nx || p->Nz_c > p->Nz) return "coarse grid must not exceed the fine grid";
   if (p->n_slices < 1) return "n_slices must be >= 1";
   if (!(p->t_end > p->t0)) return "t_end must exceed t0";
@@ -97,6 +100,16 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
     if (v == 2 || v == 4 || v == 6 || v == 8) g.MT = v;
   }
   if (g.MT > g.Mx) g.MT = g.Mx;   // Mx is a power of two >= 2
+  // keep the per-mode kernel's LDS (two FP64 tiles + staged factors) < 150 KiB
+  const size_t rb = g.mixed ? 4 : 8;
+  auto lds = [&](int mt) {
+    const size_t y = size_t(8) * 4 * mt * (g.Nz + 1);
+    const size_t n = rb * (4 * size_t(g.Pz) * mt + g.Pz);
+    const size_t f = size_t(8) * mt * 2 * ((rbc::kFacP * (g.Nz / 2 - 2) + 4) | 1);
+    const size_t u = n > f ? n : f, v = rb * size_t(g.Pz) * mt * 12;
+    return y + (y + u > v ? y + u : v);
+  };
+  while (g.MT > 2 && lds(g.MT) > 150 * 1024) g.MT = (g.MT == 6) ? 4 : g.MT / 2;
 }
 
 size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::GridPlan& c, int nsf, int nsc) {

@@ -44,129 +44,138 @@ __device__ __forceinline__ Cx<Real> csub(Cx<Real> a, Cx<Real> b) { return {a.x -
 
 // ------------------------------------------------------------------ x-pass ---
 
-// One Stockham radix-R pass over `cnt` signals of length N stored with
-// stride N: out[j + q p] = DFT_R over the twiddled in[i + r N/R] (Bainville's
-// autosort form).  sign = -1 forward, +1 inverse.
-template <typename Real, int R>
-__device__ void stockham_pass(const Cx<Real>* __restrict__ in, Cx<Real>* __restrict__ out,
-                              const Cx<Real>* __restrict__ tw, int N, int p, int cnt, Real sign) {
-  const int T = N / R;
-  const int stride_t = N / (p * R);
-  for (int w = threadIdx.x; w < cnt * T; w += blockDim.x) {
-    const int c = w / T, i = w - c * T;
+// One Stockham radix-R pass (Bainville's autosort form) over `cnt` signals
+// of length N stored with stride N, with P = product of the radices already
+// applied: out[j + q P] = DFT_R over in[i + r N/R] twiddled by
+// exp(sign 2 pi i r k / (P R)), k = i mod P, j = (i - k) R + k.  The radix
+// plan is 4, ..., 4, (2), 3, so P is a power of two in every pass and
+// r k N/(P R) < N indexes the twiddle table directly.
+template <typename Real, int R, int N, int P>
+__device__ __forceinline__ void stockham_pass(const Cx<Real>* __restrict__ in, Cx<Real>* __restrict__ out,
+                                              const Cx<Real>* __restrict__ tw, int cnt, Real sign) {
+  constexpr int T = N / R;
+  constexpr int TS = N / (P * R);
+  for (int c = 0; c < cnt; ++c) {
     const Cx<Real>* x = in + c * N;
     Cx<Real>* y = out + c * N;
-    const int k = i % p;
-    Cx<Real> a[R];
+    for (int i = threadIdx.x; i < T; i += kBlock) {
+      const int k = i & (P - 1);
+      Cx<Real> a[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      Cx<Real> v = x[i + r * T];
-      if (r > 0 && k > 0) {
-        Cx<Real> t = tw[(r * k * stride_t) % N];
-        t.y *= -sign;   // table holds exp(-2 pi i t/N); inverse uses the conjugate
-        v = cmul(v, t);
+      for (int r = 0; r < R; ++r) {
+        Cx<Real> v = x[i + r * T];
+        if (r > 0 && P > 1) {
+          Cx<Real> t = tw[r * k * TS];
+          t.y *= -sign;   // table holds exp(-2 pi i t/N); the inverse uses the conjugate
+          v = cmul(v, t);
+        }
+        a[r] = v;
       }
-      a[r] = v;
-    }
-    const int j = (i - k) * R + k;
-    if constexpr (R == 2) {
-      y[j] = cadd(a[0], a[1]);
-      y[j + p] = csub(a[0], a[1]);
-    } else if constexpr (R == 3) {
-      const Real h = Real(0.86602540378443864676);  // sqrt(3)/2
-      Cx<Real> t = cadd(a[1], a[2]), d = csub(a[1], a[2]);
-      Cx<Real> m = {a[0].x - Real(0.5) * t.x, a[0].y - Real(0.5) * t.y};
-      Cx<Real> id = {-sign * h * d.y, sign * h * d.x};   // sign * i * h * d
-      y[j] = cadd(a[0], t);
-      y[j + p] = cadd(m, id);
-      y[j + 2 * p] = csub(m, id);
-    } else {
-      Cx<Real> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
-      Cx<Real> s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
-      Cx<Real> id13 = {-sign * d13.y, sign * d13.x};      // sign * i * (a1 - a3)
-      y[j] = cadd(s02, s13);
-      y[j + p] = cadd(d02, id13);
-      y[j + 2 * p] = csub(s02, s13);
-      y[j + 3 * p] = csub(d02, id13);
+      const int j = (i - k) * R + k;
+      if constexpr (R == 2) {
+        y[j] = cadd(a[0], a[1]);
+        y[j + P] = csub(a[0], a[1]);
+      } else if constexpr (R == 3) {
+        const Real h = Real(0.86602540378443864676);  // sqrt(3)/2
+        Cx<Real> t = cadd(a[1], a[2]), d = csub(a[1], a[2]);
+        Cx<Real> m = {a[0].x - Real(0.5) * t.x, a[0].y - Real(0.5) * t.y};
+        Cx<Real> id = {-sign * h * d.y, sign * h * d.x};   // sign * i * h * d
+        y[j] = cadd(a[0], t);
+        y[j + P] = cadd(m, id);
+        y[j + 2 * P] = csub(m, id);
+      } else {
+        Cx<Real> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+        Cx<Real> s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
+        Cx<Real> id13 = {-sign * d13.y, sign * d13.x};      // sign * i * (a1 - a3)
+        y[j] = cadd(s02, s13);
+        y[j + P] = cadd(d02, id13);
+        y[j + 2 * P] = csub(s02, s13);
+        y[j + 3 * P] = csub(d02, id13);
+      }
     }
   }
 }
 
-// Runs the radix plan on cnt signals; returns the buffer holding the result.
-template <typename Real>
-__device__ Cx<Real>* fft_lds(Cx<Real>* a, Cx<Real>* b, const Cx<Real>* tw, const GridDev& g, int cnt,
-                             Real sign) {
-  int p = 1;
-  for (int st = 0; st < g.nrad; ++st) {
-    const int R = g.rad[st];
-    if (R == 3)
-      stockham_pass<Real, 3>(a, b, tw, g.Px, p, cnt, sign);
-    else if (R == 4)
-      stockham_pass<Real, 4>(a, b, tw, g.Px, p, cnt, sign);
-    else
-      stockham_pass<Real, 2>(a, b, tw, g.Px, p, cnt, sign);
+// Radix plan for N = 3 * 2^q: fours, then a two if q is odd, then the three.
+// Returns the buffer holding the result.
+template <typename Real, int N, int P>
+__device__ Cx<Real>* fft_lds(Cx<Real>* a, Cx<Real>* b, const Cx<Real>* tw, int cnt, Real sign) {
+  constexpr int rem = N / P;
+  if constexpr (rem == 1) {
+    return a;
+  } else {
+    constexpr int R = (rem == 3) ? 3 : ((rem / 3) >= 4 ? 4 : 2);
+    stockham_pass<Real, R, N, P>(a, b, tw, cnt, sign);
     __syncthreads();
-    p *= R;
-    Cx<Real>* t = a;
-    a = b;
-    b = t;
+    return fft_lds<Real, N, P * R>(b, a, tw, cnt, sign);
   }
-  return a;
 }
 
 template <typename Real>
+__device__ __forceinline__ Real wave_sum(Real v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One block per (slice, padded z point j).  Q holds the six fields of the
+// stage at the padded Gauss points, Fourier modes m < Mx; out: N_omega and
+// N_T modes m < Mx, and the horizontal mean of u w.
+template <typename Real, int PX>
 __global__ void __launch_bounds__(kBlock) xpass_kernel(GridDev g, const Real* __restrict__ Q,
                                                        Real* __restrict__ Nh, Real* __restrict__ qbar) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int Px = g.Px, Pz = g.Pz, Mx = g.Mx;
+  const int Pz = g.Pz, Mx = g.Mx;
   const int s = blockIdx.x / Pz, j = blockIdx.x - s * Pz;
-  Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem);   // [3][Px]
-  Cx<Real>* B = A + 3 * Px;                           // [3][Px]
-  Cx<Real>* tw = B + 3 * Px;                          // [Px] twiddles
-  Real* red = reinterpret_cast<Real*>(tw + Px);       // [blockDim]
+  Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem);   // [3][PX]
+  Cx<Real>* B = A + 3 * PX;                           // [3][PX]
+  Cx<Real>* tw = B + 3 * PX;                          // [PX] twiddles
+  Real* red = reinterpret_cast<Real*>(tw + PX);       // [kBlock / 64]
   const Cx<Real>* gtw = reinterpret_cast<const Cx<Real>*>(g.tw);
+  const int tid = threadIdx.x;
 
-  for (int t = threadIdx.x; t < Px; t += blockDim.x) tw[t] = gtw[t];
-  for (int t = threadIdx.x; t < 3 * Px; t += blockDim.x) A[t] = {Real(0), Real(0)};
-  __syncthreads();
+  for (int t = tid; t < PX; t += kBlock) tw[t] = gtw[t];
+  // the zero padding between the retained modes
+  const int nz0 = Mx, nzc = PX - 2 * Mx + 1;
+  for (int c = 0; c < 3; ++c)
+    for (int t = tid; t < nzc; t += kBlock) A[c * PX + nz0 + t] = {Real(0), Real(0)};
   // pack (u, w), (omega_x, omega_z), (T_x, T_z) into three complex spectra
   const size_t rowQ = size_t(Mx) * 2;
-  for (int t = threadIdx.x; t < 3 * Mx; t += blockDim.x) {
-    const int c = t / Mx, m = t - c * Mx;
-    const Real* qa = Q + ((size_t(s) * 6 + 2 * c) * Pz + j) * rowQ + 2 * m;
-    const Real* qb = Q + ((size_t(s) * 6 + 2 * c + 1) * Pz + j) * rowQ + 2 * m;
-    const Real ar = qa[0], ai = qa[1], br = qb[0], bi = qb[1];
-    A[c * Px + m] = {ar - bi, ai + br};
-    if (m > 0) A[c * Px + Px - m] = {ar + bi, br - ai};
-  }
+  const Cx<Real>* Qc = reinterpret_cast<const Cx<Real>*>(Q + (size_t(s) * 6 * Pz + j) * rowQ);
+  const size_t qs = size_t(Pz) * Mx;   // quantity stride in complex values
+  for (int c = 0; c < 3; ++c)
+    for (int m = tid; m < Mx; m += kBlock) {
+      const Cx<Real> qa = Qc[(2 * c) * qs + m], qb = Qc[(2 * c + 1) * qs + m];
+      A[c * PX + m] = {qa.x - qb.y, qa.y + qb.x};
+      if (m > 0) A[c * PX + PX - m] = {qa.x + qb.y, qb.x - qa.y};
+    }
   __syncthreads();
-  Cx<Real>* z = fft_lds<Real>(A, B, tw, g, 3, Real(1));
+  Cx<Real>* z = fft_lds<Real, PX, 1>(A, B, tw, 3, Real(1));
   Cx<Real>* o = (z == A) ? B : A;
   Real uw = 0;
-  for (int t = threadIdx.x; t < Px; t += blockDim.x) {
-    const Cx<Real> v1 = z[t], v2 = z[Px + t], v3 = z[2 * Px + t];
+  for (int t = tid; t < PX; t += kBlock) {
+    const Cx<Real> v1 = z[t], v2 = z[PX + t], v3 = z[2 * PX + t];
     const Real u = v1.x, w = v1.y;
     o[t] = {u * v2.x + w * v2.y, u * v3.x + w * v3.y};
     uw += u * w;
   }
-  red[threadIdx.x] = uw;
+  uw = wave_sum(uw);
+  if ((tid & 63) == 0) red[tid >> 6] = uw;
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
+  if (tid == 0) {
+    Real tot = 0;
+    for (int wv = 0; wv < kBlock / 64; ++wv) tot += red[wv];
+    qbar[size_t(s) * Pz + j] = tot / Real(PX);
   }
-  if (threadIdx.x == 0) qbar[size_t(s) * Pz + j] = red[0] / Real(Px);
-  Cx<Real>* Z = fft_lds<Real>(o, z, tw, g, 1, Real(-1));
-  const Real inv2 = Real(0.5) / Real(Px);
-  Real* out0 = Nh + ((size_t(s) * 2 + 0) * Pz + j) * rowQ;
-  Real* out1 = Nh + ((size_t(s) * 2 + 1) * Pz + j) * rowQ;
-  for (int m = threadIdx.x; m < Mx; m += blockDim.x) {
-    const Cx<Real> a = Z[m], b = Z[m == 0 ? 0 : Px - m];
-    // N_omega = (Z_m + conj Z_-m)/2, N_T = (Z_m - conj Z_-m)/(2i), both / Px
-    out0[2 * m] = (a.x + b.x) * inv2;
-    out0[2 * m + 1] = (a.y - b.y) * inv2;
-    out1[2 * m] = (a.y + b.y) * inv2;
-    out1[2 * m + 1] = (b.x - a.x) * inv2;
+  Cx<Real>* Z = fft_lds<Real, PX, 1>(o, z, tw, 1, Real(-1));
+  const Real inv2 = Real(0.5) / Real(PX);
+  Cx<Real>* out0 = reinterpret_cast<Cx<Real>*>(Nh + ((size_t(s) * 2 + 0) * Pz + j) * rowQ);
+  Cx<Real>* out1 = reinterpret_cast<Cx<Real>*>(Nh + ((size_t(s) * 2 + 1) * Pz + j) * rowQ);
+  for (int m = tid; m < Mx; m += kBlock) {
+    const Cx<Real> a = Z[m], b = Z[m == 0 ? 0 : PX - m];
+    // N_omega = (Z_m + conj Z_-m)/2, N_T = (Z_m - conj Z_-m)/(2i), both / PX
+    out0[m] = {(a.x + b.x) * inv2, (a.y - b.y) * inv2};
+    out1[m] = {(a.y + b.y) * inv2, (b.x - a.x) * inv2};
   }
 }
 
@@ -185,238 +194,408 @@ struct StageArgs {
   double haii;
 };
 
-// LDS strides (in doubles) of one staged factor block: odd, so that lanes
+// LDS stride (in doubles) of one staged factor block: odd, so that lanes
 // reading different blocks at the same row fall in different banks.
 __host__ __device__ __forceinline__ int lds_fac_stride(int s) { return s | 1; }
 
-// Bordered tridiagonal solve in place on v[2 i + p] (stride-2 view of one
-// parity): temperature and mean-flow systems.  fac: kFacT per row, then the
-// 1 x 1 Schur inverse.
-__device__ __forceinline__ void solve_T_format(double* v, int p, const double* fac, int nr, double gbc) {
-  double y = v[p];
-#pragma unroll 4
-  for (int i = 1; i < nr; ++i) {
-    y = v[2 * i + p] - fac[i * kFacT + 0] * y;
-    v[2 * i + p] = y;
+// Bordered tridiagonal solve in place on v[2 i + p] (one parity):
+// temperature and mean flow.  fac: kFacT entries per row, then the 1 x 1
+// Schur inverse.  NR = band rows.  With REG and up to 31 rows the parity
+// vector is held in registers for the three sweeps (shorter dependent chain,
+// more registers: the latency-bound small-batch variant); otherwise the
+// sweeps run in LDS.
+template <int NR, bool REG>
+__device__ __forceinline__ void solve_T_format(double* __restrict__ v, int p, const double* __restrict__ fac,
+                                               double gbc) {
+  if constexpr (REG && NR <= 31) {
+    double y[NR + 1];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) y[i] = v[2 * i + p];
+#pragma unroll
+    for (int i = 1; i < NR; ++i) y[i] -= fac[i * kFacT + 0] * y[i - 1];
+    double sum = 0;
+    y[NR - 1] *= fac[(NR - 1) * kFacT + 1];
+    sum = y[NR - 1];
+#pragma unroll
+    for (int i = NR - 2; i >= 0; --i) {
+      y[i] = (y[i] - fac[i * kFacT + 2] * y[i + 1]) * fac[i * kFacT + 1];
+      sum += y[i];
+    }
+    const double xh = fac[NR * kFacT] * (gbc - sum);
+    v[p] = xh;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) v[2 * (i + 1) + p] = y[i] - fac[i * kFacT + 3] * xh;
+  } else {
+    double y = v[p];
+#pragma unroll 8
+    for (int i = 1; i < NR; ++i) {
+      y = v[2 * i + p] - fac[i * kFacT + 0] * y;
+      v[2 * i + p] = y;
+    }
+    double x = y * fac[(NR - 1) * kFacT + 1];
+    v[2 * (NR - 1) + p] = x;
+    double sum = x;
+#pragma unroll 8
+    for (int i = NR - 2; i >= 0; --i) {
+      x = (v[2 * i + p] - fac[i * kFacT + 2] * x) * fac[i * kFacT + 1];
+      v[2 * i + p] = x;
+      sum += x;
+    }
+    const double xh = fac[NR * kFacT] * (gbc - sum);
+#pragma unroll 8
+    for (int i = NR - 1; i >= 0; --i) v[2 * (i + 1) + p] = v[2 * i + p] - fac[i * kFacT + 3] * xh;
+    v[p] = xh;
   }
-  double x = v[2 * (nr - 1) + p] * fac[(nr - 1) * kFacT + 1];
-  v[2 * (nr - 1) + p] = x;
-  double sum = x;
-#pragma unroll 4
-  for (int i = nr - 2; i >= 0; --i) {
-    x = (v[2 * i + p] - fac[i * kFacT + 2] * x) * fac[i * kFacT + 1];
-    v[2 * i + p] = x;
-    sum += x;
-  }
-  const double xh = fac[nr * kFacT] * (gbc - sum);
-#pragma unroll 4
-  for (int i = nr - 1; i >= 0; --i) v[2 * (i + 1) + p] = v[2 * i + p] - fac[i * kFacT + 3] * xh;
-  v[p] = xh;
 }
 
 // Bordered pentadiagonal solve in place (streamfunction, two border unknowns).
-__device__ __forceinline__ void solve_P_format(double* v, int p, const double* fac, int nr) {
-  double y2 = 0, y1 = 0;
-#pragma unroll 4
-  for (int i = 0; i < nr; ++i) {
-    const double y = v[2 * i + p] - fac[i * kFacP + 0] * y1 - fac[i * kFacP + 1] * y2;
-    v[2 * i + p] = y;
-    y2 = y1;
-    y1 = y;
+template <int NR, bool REG>
+__device__ __forceinline__ void solve_P_format(double* __restrict__ v, int p, const double* __restrict__ fac) {
+  if constexpr (REG && NR <= 31) {
+    double y[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) y[i] = v[2 * i + p];
+#pragma unroll
+    for (int i = 1; i < NR; ++i) {
+      y[i] -= fac[i * kFacP + 0] * y[i - 1];
+      if (i >= 2) y[i] -= fac[i * kFacP + 1] * y[i - 2];
+    }
+    double s0 = 0, s1 = 0;
+#pragma unroll
+    for (int i = NR - 1; i >= 0; --i) {
+      double x = y[i];
+      if (i + 1 < NR) x -= fac[i * kFacP + 3] * y[i + 1];
+      if (i + 2 < NR) x -= fac[i * kFacP + 4] * y[i + 2];
+      y[i] = x * fac[i * kFacP + 2];
+      const double nn = double(2 * (i + 2) + p);
+      s0 += y[i];
+      s1 += nn * nn * y[i];
+    }
+    const double* si = fac + NR * kFacP;
+    const double h0 = -(si[0] * s0 + si[1] * s1);
+    const double h1 = -(si[2] * s0 + si[3] * s1);
+    v[p] = h0;
+    v[2 + p] = h1;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) v[2 * (i + 2) + p] = y[i] - fac[i * kFacP + 5] * h0 - fac[i * kFacP + 6] * h1;
+  } else {
+    double y2 = 0, y1 = 0;
+#pragma unroll 8
+    for (int i = 0; i < NR; ++i) {
+      const double y = v[2 * i + p] - fac[i * kFacP + 0] * y1 - fac[i * kFacP + 1] * y2;
+      v[2 * i + p] = y;
+      y2 = y1;
+      y1 = y;
+    }
+    double x1 = 0, x2 = 0, s0 = 0, s1 = 0;
+#pragma unroll 8
+    for (int i = NR - 1; i >= 0; --i) {
+      const double x = (v[2 * i + p] - fac[i * kFacP + 3] * x1 - fac[i * kFacP + 4] * x2) * fac[i * kFacP + 2];
+      v[2 * i + p] = x;
+      const double nn = double(2 * (i + 2) + p);
+      s0 += x;
+      s1 += nn * nn * x;
+      x2 = x1;
+      x1 = x;
+    }
+    const double* si = fac + NR * kFacP;
+    const double h0 = -(si[0] * s0 + si[1] * s1);
+    const double h1 = -(si[2] * s0 + si[3] * s1);
+#pragma unroll 8
+    for (int i = NR - 1; i >= 0; --i)
+      v[2 * (i + 2) + p] = v[2 * i + p] - fac[i * kFacP + 5] * h0 - fac[i * kFacP + 6] * h1;
+    v[p] = h0;
+    v[2 + p] = h1;
   }
-  double x1 = 0, x2 = 0, s0 = 0, s1 = 0;
-#pragma unroll 4
-  for (int i = nr - 1; i >= 0; --i) {
-    const double* f = fac + i * kFacP;
-    const double x = (v[2 * i + p] - f[3] * x1 - f[4] * x2) * f[2];
-    v[2 * i + p] = x;
-    const double nn = double(2 * (i + 2) + p);
-    s0 += x;
-    s1 += nn * nn * x;
-    x2 = x1;
-    x1 = x;
-  }
-  const double* si = fac + nr * kFacP;
-  const double h0 = -(si[0] * s0 + si[1] * s1);
-  const double h1 = -(si[2] * s0 + si[3] * s1);
-#pragma unroll 4
-  for (int i = nr - 1; i >= 0; --i)
-    v[2 * (i + 2) + p] = v[2 * i + p] - fac[i * kFacP + 5] * h0 - fac[i * kFacP + 6] * h1;
-  v[p] = h0;
-  v[2 + p] = h1;
 }
 
-// Copies the factor blocks of modes m0..m0+MT-1 (both parities) into LDS.
+// Copies the factor blocks of modes m0..m0+MT-1 (both parities) into LDS,
+// eight loads in flight per thread.
 template <int MT>
 __device__ __forceinline__ void stage_factors(double* sF, const double* __restrict__ fac, int stride, int m0,
                                               int Mx) {
   const int ls = lds_fac_stride(stride);
-  const int nm = min(MT, Mx - m0);
+  const int total = min(MT, Mx - m0) * 2 * stride;
   const double* src = fac + size_t(m0) * 2 * stride;
-  for (int e = threadIdx.x; e < nm * 2 * stride; e += blockDim.x) {
-    const int b = e / stride, o = e - b * stride;
-    sF[b * ls + o] = src[e];
+  constexpr int U = 8;
+  for (int base = threadIdx.x; base < total; base += kBlock * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * kBlock;
+      v[u] = (e < total) ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * kBlock;
+      if (e < total) {
+        const int b = e / stride;
+        sF[b * ls + (e - b * stride)] = v[u];
+      }
+    }
   }
 }
 
-// LDS layout of a block (doubles first, then Real):
-//   sY  double [2 field][MT][2 re/im][Nz+1]     right-hand sides -> new stage
-//   U   union { Real sN[2][Pz][MT][2] + sq[Pz];  double sF[MT*2][odd stride] }
-template <typename Real, int MT>
+// Band-table entries of one equation row r (both equations), kept in
+// registers by the thread that owns row r.
+struct RowTables {
+  double s10[3], d2, a[3], b[5], d4;
+};
+__device__ __forceinline__ RowTables load_row_tables(const GridDev& g, int r) {
+  RowTables t;
+  const int p = r & 1, i = r >> 1, k = p * g.n + i;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) t.s10[q] = g.bS10[k * 3 + q];
+  t.d2 = g.bD2[k];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) t.a[q] = g.bA[k * 3 + q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) t.b[q] = g.bB[k * 5 + q];
+  t.d4 = g.bD4[k];
+  return t;
+}
+
+// One block per (slice, tile of MT modes).  Each thread owns one row
+// r = tid mod NZ of the equations and the columns c = tid / NZ + k (256/NZ)
+// of the tile (column c = (field, mode, re/im)).
+//
+// LDS (doubles first):
+//   sY  [2 field][MT][2][NZ+1]   right-hand sides -> new stage values
+//   sX  [2 field][MT][2][NZ+1]   old state of the tile
+//   U   union { Real sN[2][PZ][2 MT] + sq[PZ];  double sF[2 MT][odd stride] }
+template <typename Real, int NZ, int MT>
 __global__ void __launch_bounds__(kBlock)
 stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __restrict__ qbar,
              double* __restrict__ X, Real* __restrict__ Ehist, double* __restrict__ LYhist,
              Real* __restrict__ Q, double* __restrict__ Eout) {
+  constexpr int PZ = 3 * NZ / 2, PH = PZ / 2, LD = NZ + 1, NH = NZ / 2;
+  constexpr int NRT = NH - 1, NRP = NH - 2;
+  constexpr int NC = 4 * MT;                 // columns (field, mode, re/im)
+  constexpr int CR = kBlock / NZ;            // columns in parallel
+  constexpr int KC = (NC + CR - 1) / CR;     // columns per thread
+  // Two-mode tiles serve the latency-bound launches (the single-slice coarse
+  // sweep, the largest Nz): more work items per phase and register-held
+  // solves.  Wider tiles serve the throughput-bound batched launches.
+  constexpr bool kWide = (MT <= 2);
+  static_assert(kBlock % NZ == 0, "NZ must divide the block size");
   extern __shared__ __align__(16) unsigned char smem[];
-  const int Nz = g.Nz, Mx = g.Mx, Pz = g.Pz, Ph = Pz / 2, LD = Nz + 1;
+  const int Mx = g.Mx;
   const int ntile = (Mx + MT - 1) / MT;
   const int s = blockIdx.x / ntile, tile = blockIdx.x - s * ntile;
   const int m0 = tile * MT;
   const int st = g.state;
   double* sY = reinterpret_cast<double*>(smem);
-  unsigned char* uni = smem + sizeof(double) * 4 * MT * LD;
+  double* sX = sY + 4 * MT * LD;
+  unsigned char* uni = reinterpret_cast<unsigned char*>(sX + 4 * MT * LD);
   Real* sN = reinterpret_cast<Real*>(uni);
-  Real* sq = sN + 4 * Pz * MT;
+  Real* sq = sN + 4 * PZ * MT;
   double* sF = reinterpret_cast<double*>(uni);
-  auto yi = [&](int f, int mt, int ri) { return ((f * MT + mt) * 2 + ri) * LD; };
-  auto gidx = [&](int f, int m, int ri) { return size_t(((f * Mx + m) * 2 + ri)) * Nz; };
+  const int tid = threadIdx.x;
+  const int r = tid % NZ, c0 = tid / NZ;     // this thread's row and first column
+  // column c -> (field, mode within tile, re/im); LDS and HBM offsets
+  auto fld = [](int c) { return c / (2 * MT); };
+  auto mtc = [](int c) { return (c >> 1) % MT; };
+  auto yoff = [](int c) { return c * LD; };  // == ((f MT + mt) 2 + ri) LD
+  auto goff = [&](int c) {
+    return size_t((fld(c) * Mx + m0 + mtc(c)) * 2 + (c & 1)) * NZ;
+  };
   const double* Xs = X + size_t(s) * st;
-  const int tid = threadIdx.x, nth = blockDim.x;
 
   if (a.mode == kModeZinv) {
-    for (int e = tid; e < 4 * MT * Nz; e += nth) {
-      const int nn = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
-      const int m = m0 + mt;
-      sY[yi(f, mt, ri) + nn] = (m < Mx) ? Xs[gidx(f, m, ri) + nn] : 0.0;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const int c = c0 + kc * CR;
+      if (c < NC) sY[yoff(c) + r] = (m0 + mtc(c) < Mx) ? Xs[goff(c) + r] : 0.0;
     }
     __syncthreads();
   } else {
-    // ---- phase A: products of this tile on the padded Gauss points
-    // (8 loads in flight per thread before the LDS stores)
+    // ---- phase A: products of this tile on the padded Gauss points, and
+    // the old state (eight loads in flight per thread)
     const size_t rowQ = size_t(Mx) * 2;
     {
       constexpr int U = 8;
-      const int total = 4 * Pz * MT;
-      for (int base = tid; base < total; base += nth * U) {
+      constexpr int total = 4 * PZ * MT;
+      for (int base = tid; base < total; base += kBlock * U) {
         Real v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int e = base + u * nth;
+          const int e = base + u * kBlock;
           v[u] = Real(0);
           if (e < total) {
-            const int c = e % (2 * MT), j = (e / (2 * MT)) % Pz, qq = e / (2 * MT * Pz);
-            if (m0 + (c >> 1) < Mx) v[u] = Nh[((size_t(s) * 2 + qq) * Pz + j) * rowQ + 2 * m0 + c];
+            const int c = e % (2 * MT), jq = e / (2 * MT);   // jq = qq * PZ + j
+            if (m0 + (c >> 1) < Mx) v[u] = Nh[(size_t(s) * 2 * PZ + jq) * rowQ + 2 * m0 + c];
           }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int e = base + u * nth;
+          const int e = base + u * kBlock;
           if (e < total) sN[e] = v[u];
         }
       }
     }
     if (m0 == 0)
-      for (int j = tid; j < Pz; j += nth) sq[j] = qbar[size_t(s) * Pz + j];
+      for (int j = tid; j < PZ; j += kBlock) sq[j] = qbar[size_t(s) * PZ + j];
+    if (a.mode == kModeStage) {
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        if (c < NC) sX[yoff(c) + r] = (m0 + mtc(c) < Mx) ? Xs[goff(c) + r] : 0.0;
+      }
+    }
     __syncthreads();
-    // ---- phase B: explicit terms of the previous stage on the band rows.
-    // Item (f, r): one row of the folded forward map against every column
-    // (mode, re/im) of the tile; the u_bar column of mode 0 separately.
     const Real* W = reinterpret_cast<const Real*>(g.Wfwd);
-    const int nitems = 2 * Nz + (m0 == 0 ? Nz : 0);
-    for (int e = tid; e < nitems; e += nth) {
-      const int r = e % Nz, f = e / Nz;   // f = 2: the u_bar column
-      const int rows = (f == 0) ? Nz - 4 : Nz - 2;
+    // writes the explicit terms of item (f, row) to LDS (scaled) and HBM
+    auto store_explicit = [&](int f, int rr, const Real* acc) {
       if (f == 2) {
-        double E = 0.0;
-        if (r < Nz - 2) {
-          const Real* w = W + (size_t(2) * Nz + r) * Ph;
-          const Real sg = (r & 1) ? Real(1) : Real(-1);
-          Real acc = 0;
-#pragma unroll 8
-          for (int j = 0; j < Ph; ++j) acc += w[j] * (sq[j] + sg * sq[Pz - 1 - j]);
-          E = double(acc);
-        }
+        const double E = double(acc[0]);
+        const size_t o0 = size_t(0) * NZ + rr, o1 = size_t(1) * NZ + rr;   // field 0, m 0, re / im
         if (a.mode == kModeExplicit) {
-          Eout[gidx(0, 0, 0) + r] = E;
-          Eout[gidx(0, 0, 1) + r] = 0.0;
+          Eout[o0] = E;
+          Eout[o1] = 0.0;
         } else {
-          sY[yi(0, 0, 0) + r] = a.hae[a.stage - 1] * E;
-          sY[yi(0, 0, 1) + r] = 0.0;
+          sY[0 * LD + rr] = a.hae[a.stage - 1] * E;
+          sY[1 * LD + rr] = 0.0;
           if (a.store_E) {
             Real* eh = Ehist + (size_t(a.stage - 1) * a.cap + s) * st;
-            eh[gidx(0, 0, 0) + r] = Real(E);
-            eh[gidx(0, 0, 1) + r] = Real(0);
+            eh[o0] = Real(E);
+            eh[o1] = Real(0);
           }
         }
-        continue;
+        return;
       }
+#pragma unroll
+      for (int cc = 0; cc < 2 * MT; ++cc) {
+        const int mt = cc >> 1, ri = cc & 1, m = m0 + mt;
+        if (m >= Mx || (f == 0 && m == 0)) continue;
+        const double E = double(acc[cc]);
+        const size_t off = size_t((f * Mx + m) * 2 + ri) * NZ + rr;
+        if (a.mode == kModeExplicit) {
+          Eout[off] = E;
+        } else {
+          sY[((f * MT + mt) * 2 + ri) * LD + rr] = a.hae[a.stage - 1] * E;
+          if (a.store_E) Ehist[(size_t(a.stage - 1) * a.cap + s) * st + off] = Real(E);
+        }
+      }
+    };
+    // ---- phase B: explicit terms of the previous stage on the band rows.
+    // Item (f, row): one row of the folded forward map against every column
+    // (mode, re/im) of the field; item f = 2 is the u_bar column of mode 0.
+    if constexpr (kWide) {
+      // two-mode tiles: each item split over JS lanes that take every JS-th
+      // Gauss point, summed by shuffles
+    constexpr int JS = 4;
+    const int nitems = ((m0 == 0) ? 3 : 2) * NZ;
+    for (int e = tid; e < nitems * JS; e += kBlock) {
+      const int lane = e & (JS - 1), item = e / JS;
+      const int rr = item % NZ, f = item / NZ;
       Real acc[2 * MT];
 #pragma unroll
       for (int c = 0; c < 2 * MT; ++c) acc[c] = Real(0);
-      if (r < rows) {
-        const Real* w = W + (size_t(f == 0 ? 0 : 1) * Nz + r) * Ph;
-        const Real* src = sN + (f == 0 ? 0 : Pz * 2 * MT);
-        const Real sg = (r & 1) ? Real(-1) : Real(1);
-#pragma unroll 8
-        for (int j = 0; j < Ph; ++j) {
+      if (f == 2) {
+        if (rr < NZ - 2) {
+          const Real* w = W + (size_t(2) * NZ + rr) * PH;
+          const Real sg = (rr & 1) ? Real(1) : Real(-1);
+#pragma unroll 4
+          for (int j = lane; j < PH; j += JS) acc[0] += w[j] * (sq[j] + sg * sq[PZ - 1 - j]);
+        }
+      } else if (rr < ((f == 0) ? NZ - 4 : NZ - 2)) {
+        const Real* w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
+        const Real* src = sN + (f == 0 ? 0 : PZ * 2 * MT);
+        const Real sg = (rr & 1) ? Real(-1) : Real(1);
+#pragma unroll 4
+        for (int j = lane; j < PH; j += JS) {
           const Real wv = w[j];
           const Real* a0 = src + j * 2 * MT;
-          const Real* a1 = src + (Pz - 1 - j) * 2 * MT;
+          const Real* a1 = src + (PZ - 1 - j) * 2 * MT;
 #pragma unroll
           for (int c = 0; c < 2 * MT; ++c) acc[c] += wv * (a0[c] + sg * a1[c]);
         }
       }
 #pragma unroll
       for (int c = 0; c < 2 * MT; ++c) {
-        const int mt = c >> 1, ri = c & 1, m = m0 + mt;
-        if (m >= Mx || (f == 0 && m == 0)) continue;
-        const double E = double(acc[c]);
-        if (a.mode == kModeExplicit) {
-          Eout[gidx(f, m, ri) + r] = E;
-        } else {
-          sY[yi(f, mt, ri) + r] = a.hae[a.stage - 1] * E;
-          if (a.store_E) Ehist[(size_t(a.stage - 1) * a.cap + s) * st + gidx(f, m, ri) + r] = Real(E);
+        acc[c] += __shfl_xor(acc[c], 1, JS);
+        acc[c] += __shfl_xor(acc[c], 2, JS);
+      }
+      if (lane != 0) continue;
+      store_explicit(f, rr, acc);
+    }
+    } else {
+      // wider tiles: one item per thread
+    const int nitems = ((m0 == 0) ? 3 : 2) * NZ;
+    for (int e = tid; e < nitems; e += kBlock) {
+      const int rr = e % NZ, f = e / NZ;
+      Real acc[2 * MT];
+#pragma unroll
+      for (int c = 0; c < 2 * MT; ++c) acc[c] = Real(0);
+      if (f == 2) {
+        if (rr < NZ - 2) {
+          const Real* w = W + (size_t(2) * NZ + rr) * PH;
+          const Real sg = (rr & 1) ? Real(1) : Real(-1);
+#pragma unroll 8
+          for (int j = 0; j < PH; ++j) acc[0] += w[j] * (sq[j] + sg * sq[PZ - 1 - j]);
+        }
+      } else if (rr < ((f == 0) ? NZ - 4 : NZ - 2)) {
+        const Real* w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
+        const Real* src = sN + (f == 0 ? 0 : PZ * 2 * MT);
+        const Real sg = (rr & 1) ? Real(-1) : Real(1);
+#pragma unroll 4
+        for (int j = 0; j < PH; ++j) {
+          const Real wv = w[j];
+          const Real* a0 = src + j * 2 * MT;
+          const Real* a1 = src + (PZ - 1 - j) * 2 * MT;
+#pragma unroll
+          for (int c = 0; c < 2 * MT; ++c) acc[c] += wv * (a0[c] + sg * a1[c]);
         }
       }
+      store_explicit(f, rr, acc);
+    }
     }
     if (a.mode == kModeExplicit) return;
     __syncthreads();
     // temperature factors into the (now free) union region
     stage_factors<MT>(sF, g.facT, g.facT_stride, m0, Mx);
-    // ---- phase C: right-hand side of stage i on the band rows
-#pragma unroll 4
-    for (int e = tid; e < 4 * MT * Nz; e += nth) {
-      const int r = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
-      const int m = m0 + mt;
-      if (m >= Mx) continue;
-      const bool psi = (f == 0 && m > 0);
-      const int rows = psi ? Nz - 4 : Nz - 2;
-      if (r >= rows) continue;
-      const int p = r & 1, i = r >> 1;
-      const double* xv = Xs + gidx(f, m, ri);
-      double MX = 0;
-      if (!psi) {
-        const double* b = g.bS10 + (p * g.n + i) * 3;
-        for (int t = 0; t < 3; ++t)
-          if (r + 2 * t < Nz) MX += b[t] * xv[r + 2 * t];
-      } else {
-        const double k = m * g.kscale;
-        const double* bA = g.bA + (p * g.n + i) * 3;
-        const double* bB = g.bB + (p * g.n + i) * 5;
-        double sa = 0, sb = 0;
-        for (int t = 0; t < 3; ++t)
-          if (r + 2 + 2 * t < Nz) sa += bA[t] * xv[r + 2 + 2 * t];
-        for (int t = 0; t < 5; ++t)
-          if (r + 2 * t < Nz) sb += bB[t] * xv[r + 2 * t];
-        MX = sa - k * k * sb;
+    // ---- phase C: right-hand side of stage i on this thread's row
+    const RowTables tb = load_row_tables(g, r);
+    {
+      double acc[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        acc[kc] = 0.0;
+        if (c >= NC) continue;
+        const int f = fld(c), m = m0 + mtc(c);
+        if (m >= Mx) continue;
+        const bool psi = (f == 0 && m > 0);
+        if (r >= (psi ? NZ - 4 : NZ - 2)) continue;
+        const double* xv = sX + yoff(c);
+        double MX;
+        if (!psi) {
+          MX = tb.s10[0] * xv[r] + tb.s10[1] * xv[r + 2] + (r + 4 < NZ ? tb.s10[2] * xv[r + 4] : 0.0);
+        } else {
+          const double k = m * g.kscale;
+          double sa = 0, sb = 0;
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            if (r + 2 + 2 * t < NZ) sa += tb.a[t] * xv[r + 2 + 2 * t];
+#pragma unroll
+          for (int t = 0; t < 5; ++t)
+            if (r + 2 * t < NZ) sb += tb.b[t] * xv[r + 2 * t];
+          MX = sa - k * k * sb;
+        }
+        const size_t off = goff(c) + r;
+        double h = MX + sY[yoff(c) + r];
+        for (int jj = 0; jj + 1 < a.stage; ++jj)
+          h += a.hae[jj] * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
+        for (int jj = 1; jj < a.stage; ++jj)
+          h += a.hai[jj] * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
+        acc[kc] = h;
       }
-      double acc = MX + sY[yi(f, mt, ri) + r];
-      const size_t off = gidx(f, m, ri) + r;
-      for (int jj = 0; jj + 1 < a.stage; ++jj)
-        acc += a.hae[jj] * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
-      for (int jj = 1; jj < a.stage; ++jj)
-        acc += a.hai[jj] * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
-      sY[yi(f, mt, ri) + r] = acc;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        if (c < NC && m0 + mtc(c) < Mx && r < ((fld(c) == 0 && m0 + mtc(c) > 0) ? NZ - 4 : NZ - 2))
+          sY[yoff(c) + r] = acc[kc];
+      }
     }
     __syncthreads();
     // ---- phase D: temperature solves, lanes (mode, parity, re/im)
@@ -425,89 +604,180 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       if (m < Mx) {
         double gbc = 0.0;
         if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
-        solve_T_format(sY + yi(1, mt, ri), p, sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), g.nrT, gbc);
+        solve_T_format<NRT, kWide>(sY + ((MT + mt) * 2 + ri) * LD, p,
+                            sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc);
       }
     }
     __syncthreads();
     // flow factors; implicit buoyancy of the new temperature into psi
     stage_factors<MT>(sF, g.facP, g.facP_stride, m0, Mx);
-    for (int e = tid; e < 2 * MT * Nz; e += nth) {
-      const int r = e % Nz, c = e / Nz, ri = c & 1, mt = c >> 1, m = m0 + mt;
-      if (m >= Mx || m == 0 || r >= Nz - 4) continue;
-      const int p = r & 1, i = r >> 1;
-      const double k = m * g.kscale;
-      const double* bB = g.bB + (p * g.n + i) * 5;
-      const double* tv = sY + yi(1, mt, ri ^ 1);
-      double sb = 0;
-      for (int t = 0; t < 5; ++t)
-        if (r + 2 * t < Nz) sb += bB[t] * tv[r + 2 * t];
-      sY[yi(0, mt, ri) + r] += a.haii * (ri == 0 ? k * sb : -k * sb);
+    if (r < NZ - 4) {
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;          // only field-0 columns (c < 2 MT)
+        if (c >= 2 * MT) continue;
+        const int mt = c >> 1, ri = c & 1, m = m0 + mt;
+        if (m >= Mx || m == 0) continue;
+        const double k = m * g.kscale;
+        const double* tv = sY + ((MT + mt) * 2 + (ri ^ 1)) * LD;
+        double sb = 0;
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+          if (r + 2 * t < NZ) sb += tb.b[t] * tv[r + 2 * t];
+        sY[yoff(c) + r] += a.haii * (ri == 0 ? k * sb : -k * sb);
+      }
     }
     __syncthreads();
     if (tid < 4 * MT) {
       const int mt = tid >> 2, p = (tid >> 1) & 1, ri = tid & 1, m = m0 + mt;
       if (m < Mx) {
         const double* fac = sF + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
+        double* v = sY + (mt * 2 + ri) * LD;
         if (m == 0)
-          solve_T_format(sY + yi(0, mt, ri), p, fac, g.nrT, 0.0);
+          solve_T_format<NRT, kWide>(v, p, fac, 0.0);
         else
-          solve_P_format(sY + yi(0, mt, ri), p, fac, g.nrP);
+          solve_P_format<NRP, kWide>(v, p, fac);
       }
     }
     __syncthreads();
     // ---- phase F: L Y_i for later stages; the new state at the last stage
     if (a.store_LY) {
-      for (int e = tid; e < 4 * MT * Nz; e += nth) {
-        const int r = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
-        const int m = m0 + mt;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        if (c >= NC) continue;
+        const int f = fld(c), mt = mtc(c), ri = c & 1, m = m0 + mt;
         if (m >= Mx) continue;
         const bool psi = (f == 0 && m > 0);
-        if (r >= (psi ? Nz - 4 : Nz - 2)) continue;
-        const int p = r & 1, i = r >> 1;
-        const double* yv = sY + yi(f, mt, ri);
+        if (r >= (psi ? NZ - 4 : NZ - 2)) continue;
+        const double* yv = sY + yoff(c);
         const double k = m * g.kscale, k2 = k * k;
         double L;
         if (f == 1) {
-          const double* b = g.bS10 + (p * g.n + i) * 3;
-          double sm = 0;
-          for (int t = 0; t < 3; ++t)
-            if (r + 2 * t < Nz) sm += b[t] * yv[r + 2 * t];
-          L = g.kappa * (g.bD2[p * g.n + i] * yv[r + 2] - k2 * sm);
+          const double sm = tb.s10[0] * yv[r] + tb.s10[1] * yv[r + 2] + (r + 4 < NZ ? tb.s10[2] * yv[r + 4] : 0.0);
+          L = g.kappa * (tb.d2 * yv[r + 2] - k2 * sm);
         } else if (m == 0) {
-          L = g.nu * g.bD2[p * g.n + i] * yv[r + 2];
+          L = g.nu * tb.d2 * yv[r + 2];
         } else {
-          const double* bA = g.bA + (p * g.n + i) * 3;
-          const double* bB = g.bB + (p * g.n + i) * 5;
-          const double* tv = sY + yi(1, mt, ri ^ 1);
+          const double* tv = sY + ((MT + mt) * 2 + (ri ^ 1)) * LD;
           double sa = 0, sb = 0, st5 = 0;
+#pragma unroll
           for (int t = 0; t < 3; ++t)
-            if (r + 2 + 2 * t < Nz) sa += bA[t] * yv[r + 2 + 2 * t];
+            if (r + 2 + 2 * t < NZ) sa += tb.a[t] * yv[r + 2 + 2 * t];
+#pragma unroll
           for (int t = 0; t < 5; ++t)
-            if (r + 2 * t < Nz) {
-              sb += bB[t] * yv[r + 2 * t];
-              st5 += bB[t] * tv[r + 2 * t];
+            if (r + 2 * t < NZ) {
+              sb += tb.b[t] * yv[r + 2 * t];
+              st5 += tb.b[t] * tv[r + 2 * t];
             }
-          L = g.nu * (g.bD4[p * g.n + i] * yv[r + 4] - 2.0 * k2 * sa + k2 * k2 * sb) +
-              (ri == 0 ? k * st5 : -k * st5);
+          L = g.nu * (tb.d4 * yv[r + 4] - 2.0 * k2 * sa + k2 * k2 * sb) + (ri == 0 ? k * st5 : -k * st5);
         }
-        LYhist[(size_t(a.stage - 1) * a.cap + s) * st + gidx(f, m, ri) + r] = L;
+        LYhist[(size_t(a.stage - 1) * a.cap + s) * st + goff(c) + r] = L;
       }
     }
     if (a.write_X) {
       double* Xw = X + size_t(s) * st;
-      for (int e = tid; e < 4 * MT * Nz; e += nth) {
-        const int nn = e % Nz, c = e / Nz, ri = c & 1, mt = (c >> 1) % MT, f = c / (2 * MT);
-        const int m = m0 + mt;
-        if (m < Mx) Xw[gidx(f, m, ri) + nn] = sY[yi(f, mt, ri) + nn];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        if (c < NC && m0 + mtc(c) < Mx) Xw[goff(c) + r] = sY[yoff(c) + r];
       }
     }
     if (!a.do_zinv) return;
   }
   // ---- phase G: values and z-derivatives of the new stage at the padded
-  // Gauss points j and Pz-1-j, six quantities per mode (m contiguous in HBM)
+  // Gauss points, six quantities per mode (m contiguous in HBM).
+  // Two-mode tiles: pass 1, item (column, j < PZ/2): the products
+  // E D^q c (q = 0..3 for psi / u_bar, 0..1 for T) at j and, by reflection,
+  // at PZ-1-j, into sV (the old-state tile and the union are dead here).
+  // Pass 2, item (j, mode): the six quantities, written m-contiguous.
+  if constexpr (kWide) {
+  {
+    Real* sV = reinterpret_cast<Real*>(sX);   // [PZ][MT][2 re/im][6]
+    const Real* Wi = reinterpret_cast<const Real*>(g.Winv);
+    for (int e = tid; e < PH * NC; e += kBlock) {
+      // field-major order keeps the four-product (psi) items together
+      const int f = e / (PH * 2 * MT), e2 = e - f * (PH * 2 * MT);
+      const int cc = e2 % (2 * MT), j = e2 / (2 * MT);
+      const int mt = cc >> 1, ri = cc & 1, m = m0 + mt;
+      if (m >= Mx) continue;
+      const double* yv = sY + ((f * MT + mt) * 2 + ri) * LD;
+      Real acc[2][4];
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[pp][q] = Real(0);
+      const Real* w = Wi + size_t(j) * NZ;
+      constexpr size_t QS = size_t(PH) * NZ;
+      if (f == 0) {
+#pragma unroll 4
+        for (int nn = 0; nn < NZ; nn += 2) {
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp) {
+            const Real cv = Real(yv[nn + pp]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[pp][q] += w[q * QS + nn + pp] * cv;
+          }
+        }
+      } else {
+#pragma unroll 4
+        for (int nn = 0; nn < NZ; nn += 2) {
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp) {
+            const Real cv = Real(yv[nn + pp]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) acc[pp][q] += w[q * QS + nn + pp] * cv;
+          }
+        }
+      }
+      const int slot0 = (f == 0) ? 0 : 4, nq = (f == 0) ? 4 : 2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q >= nq) break;
+        // d^q T_n / dz^q at the reflected point is (-1)^(n+q) times that at j
+        const Real lo = acc[0][q] + acc[1][q], hi = acc[0][q] - acc[1][q];
+        sV[((j * MT + mt) * 2 + ri) * 6 + slot0 + q] = lo;
+        sV[(((PZ - 1 - j) * MT + mt) * 2 + ri) * 6 + slot0 + q] = (q & 1) ? -hi : hi;
+      }
+    }
+    __syncthreads();
+    const size_t rowQ = size_t(Mx) * 2;
+    for (int e = tid; e < PZ * MT; e += kBlock) {
+      const int mt = e % MT, jj = e / MT, m = m0 + mt;
+      if (m >= Mx) continue;
+      const Real* vr = sV + (jj * MT + mt) * 12;       // re: [0..5], im: [6..11]
+      const Real* vi = vr + 6;
+      const Real k = Real(m * g.kscale), k2 = k * k;
+      Real out[6][2];
+      if (m > 0) {
+        out[0][0] = vr[1]; out[0][1] = vi[1];                            // u = psi_z
+        out[1][0] = k * vi[0]; out[1][1] = -k * vr[0];                   // w = -i k psi
+        const Real omr = vr[2] - k2 * vr[0], omi = vi[2] - k2 * vi[0];
+        out[2][0] = -k * omi; out[2][1] = k * omr;                       // omega_x = i k omega
+        out[3][0] = vr[3] - k2 * vr[1]; out[3][1] = vi[3] - k2 * vi[1];  // omega_z
+        out[4][0] = -k * vi[4]; out[4][1] = k * vr[4];                   // T_x = i k T
+        out[5][0] = vr[5]; out[5][1] = vi[5];                            // T_z
+      } else {
+        out[0][0] = vr[0]; out[0][1] = 0;                                // u = u_bar
+        out[1][0] = 0; out[1][1] = 0;
+        out[2][0] = 0; out[2][1] = 0;
+        out[3][0] = vr[2]; out[3][1] = 0;                                // omega_z = u_bar_zz
+        out[4][0] = 0; out[4][1] = 0;
+        out[5][0] = vr[5]; out[5][1] = 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        Cx<Real>* d = reinterpret_cast<Cx<Real>*>(Q + ((size_t(s) * 6 + q) * PZ + jj) * rowQ) + m;
+        *d = {out[q][0], out[q][1]};
+      }
+    }
+  }
+  } else {
+  // wider tiles: item (j < PZ/2, mode) computes all six products and
+  // quantities at j and PZ-1-j directly (fewer map loads per column)
   const Real* Wi = reinterpret_cast<const Real*>(g.Winv);
   const size_t rowQ = size_t(Mx) * 2;
-  for (int e = tid; e < Ph * MT; e += nth) {
+  for (int e = tid; e < PH * MT; e += kBlock) {
     const int mt = e % MT, j = e / MT, m = m0 + mt;
     if (m >= Mx) continue;
     // acc[parity][q][re/im]: q = 0..3 on psi (E D^q psi), 4..5 on T (E, E D)
@@ -516,16 +786,16 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
       for (int q = 0; q < 6; ++q) acc[pp][q][0] = acc[pp][q][1] = Real(0);
-    const double* pr = sY + yi(0, mt, 0);
-    const double* pi = sY + yi(0, mt, 1);
-    const double* tr = sY + yi(1, mt, 0);
-    const double* ti = sY + yi(1, mt, 1);
-    const Real* w0 = Wi + (size_t(0) * Ph + j) * Nz;
-    const Real* w1 = Wi + (size_t(1) * Ph + j) * Nz;
-    const Real* w2 = Wi + (size_t(2) * Ph + j) * Nz;
-    const Real* w3 = Wi + (size_t(3) * Ph + j) * Nz;
+    const double* pr = sY + (mt * 2 + 0) * LD;
+    const double* pi = sY + (mt * 2 + 1) * LD;
+    const double* tr = sY + ((MT + mt) * 2 + 0) * LD;
+    const double* ti = sY + ((MT + mt) * 2 + 1) * LD;
+    const Real* w0 = Wi + (size_t(0) * PH + j) * NZ;
+    const Real* w1 = Wi + (size_t(1) * PH + j) * NZ;
+    const Real* w2 = Wi + (size_t(2) * PH + j) * NZ;
+    const Real* w3 = Wi + (size_t(3) * PH + j) * NZ;
 #pragma unroll 4
-    for (int nn = 0; nn < Nz; nn += 2) {
+    for (int nn = 0; nn < NZ; nn += 2) {
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp) {
         const int c = nn + pp;
@@ -544,7 +814,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     const int qord[6] = {0, 1, 2, 3, 0, 1};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int jj = side ? Pz - 1 - j : j;
+      const int jj = side ? PZ - 1 - j : j;
       Real v[6][2];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
@@ -572,11 +842,11 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        Real* d = Q + ((size_t(s) * 6 + q) * Pz + jj) * rowQ + 2 * m;
-        d[0] = out[q][0];
-        d[1] = out[q][1];
+        Cx<Real>* d = reinterpret_cast<Cx<Real>*>(Q + ((size_t(s) * 6 + q) * PZ + jj) * rowQ) + m;
+        *d = {out[q][0], out[q][1]};
       }
     }
+  }
   }
 }
 
@@ -708,46 +978,79 @@ __global__ void defect_kernel(const double* __restrict__ part, int first, int la
 
 namespace {
 
-size_t stage_lds(const GridDev& d, size_t rb) {
-  const size_t y = sizeof(double) * 4 * d.MT * (d.Nz + 1);
-  const size_t n = rb * (4 * size_t(d.Pz) * d.MT + d.Pz);
-  const int fs = d.facT_stride > d.facP_stride ? d.facT_stride : d.facP_stride;
-  const size_t f = sizeof(double) * size_t(d.MT) * 2 * lds_fac_stride(fs);
-  return y + (n > f ? n : f);
-}
-size_t xpass_lds(const GridDev& d, size_t rb) {
-  return rb * 2 * (7 * size_t(d.Px)) + rb * kBlock;
+template <int NZ, int MT>
+constexpr size_t stage_lds_t(size_t rb, int fac_stride) {
+  constexpr size_t PZ = 3 * NZ / 2;
+  const size_t tile = sizeof(double) * 4 * MT * (NZ + 1);
+  const size_t nh = rb * (4 * PZ * MT + PZ);
+  const size_t fac = sizeof(double) * size_t(MT) * 2 * (fac_stride | 1);
+  const size_t uni = nh > fac ? nh : fac;
+  const size_t vals = rb * PZ * MT * 12;
+  return tile + (tile + uni > vals ? tile + uni : vals);
 }
 
-template <typename Real, int MT>
-hipError_t run_stage_mt(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
-                        hipStream_t st) {
+template <typename Real, int NZ, int MT>
+hipError_t run_stage_t(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
+                       hipStream_t st) {
   const GridDev& d = g.dev;
   const int ntile = (d.Mx + MT - 1) / MT;
-  hipLaunchKernelGGL((stage_kernel<Real, MT>), dim3(n_slices * ntile), dim3(kBlock), stage_lds(d, sizeof(Real)),
-                     st, d, a, (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q,
-                     Eout);
+  const int fs = d.facT_stride > d.facP_stride ? d.facT_stride : d.facP_stride;
+  const size_t lds = stage_lds_t<NZ, MT>(sizeof(Real), fs);
+  hipLaunchKernelGGL((stage_kernel<Real, NZ, MT>), dim3(n_slices * ntile), dim3(kBlock), lds, st, d, a,
+                     (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q, Eout);
   return hipGetLastError();
 }
 
-template <typename Real>
-hipError_t run_stage(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
-                     hipStream_t st) {
+template <typename Real, int NZ>
+hipError_t run_stage_nz(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
+                        hipStream_t st) {
   switch (g.dev.MT) {
-    case 2: return run_stage_mt<Real, 2>(g, w, a, X, n_slices, Eout, st);
-    case 4: return run_stage_mt<Real, 4>(g, w, a, X, n_slices, Eout, st);
-    case 6: return run_stage_mt<Real, 6>(g, w, a, X, n_slices, Eout, st);
-    case 8: return run_stage_mt<Real, 8>(g, w, a, X, n_slices, Eout, st);
+    case 2: return run_stage_t<Real, NZ, 2>(g, w, a, X, n_slices, Eout, st);
+    case 4: return run_stage_t<Real, NZ, 4>(g, w, a, X, n_slices, Eout, st);
+    case 6: return run_stage_t<Real, NZ, 6>(g, w, a, X, n_slices, Eout, st);
+    case 8: return run_stage_t<Real, NZ, 8>(g, w, a, X, n_slices, Eout, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename Real>
-hipError_t run_xpass(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
+hipError_t run_stage(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
+                     hipStream_t st) {
+  switch (g.dev.Nz) {
+    case 8: return run_stage_nz<Real, 8>(g, w, a, X, n_slices, Eout, st);
+    case 16: return run_stage_nz<Real, 16>(g, w, a, X, n_slices, Eout, st);
+    case 32: return run_stage_nz<Real, 32>(g, w, a, X, n_slices, Eout, st);
+    case 64: return run_stage_nz<Real, 64>(g, w, a, X, n_slices, Eout, st);
+    case 128: return run_stage_nz<Real, 128>(g, w, a, X, n_slices, Eout, st);
+    case 256: return run_stage_nz<Real, 256>(g, w, a, X, n_slices, Eout, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Real, int PX>
+hipError_t run_xpass_t(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
   const GridDev& d = g.dev;
-  hipLaunchKernelGGL(xpass_kernel<Real>, dim3(n_slices * d.Pz), dim3(kBlock), xpass_lds(d, sizeof(Real)), st,
-                     d, (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar);
+  const size_t lds = sizeof(Real) * 2 * 7 * size_t(PX) + sizeof(Real) * (kBlock / 64);
+  hipLaunchKernelGGL((xpass_kernel<Real, PX>), dim3(n_slices * d.Pz), dim3(kBlock), lds, st, d, (const Real*)w.Q,
+                     (Real*)w.Nh, (Real*)w.qbar);
   return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t run_xpass(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
+  switch (g.dev.Px) {
+    case 6: return run_xpass_t<Real, 6>(g, w, n_slices, st);
+    case 12: return run_xpass_t<Real, 12>(g, w, n_slices, st);
+    case 24: return run_xpass_t<Real, 24>(g, w, n_slices, st);
+    case 48: return run_xpass_t<Real, 48>(g, w, n_slices, st);
+    case 96: return run_xpass_t<Real, 96>(g, w, n_slices, st);
+    case 192: return run_xpass_t<Real, 192>(g, w, n_slices, st);
+    case 384: return run_xpass_t<Real, 384>(g, w, n_slices, st);
+    case 768: return run_xpass_t<Real, 768>(g, w, n_slices, st);
+    case 1536: return run_xpass_t<Real, 1536>(g, w, n_slices, st);
+    case 3072: return run_xpass_t<Real, 3072>(g, w, n_slices, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Records an event of the timing pool (start or stop of one launch).
