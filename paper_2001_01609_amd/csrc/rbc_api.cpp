@@ -66,9 +66,8 @@ std::string check_params(const rbc_params* p) {
     return "Nx and Nx_c must be powers of two >= 4 (padded grid 3 Nx / 2)";
   if (!pow2(p->Nz) || p->Nz < 8 || p->Nz > 256 || !pow2(p->Nz_c) || p->Nz_c < 8)
     return "Nz and Nz_c must be powers of two in [8, 256]";
-  // the x-pass keeps seven padded rows of complex values in LDS (160 KiB)
-  if (p->Nx > (p->precision == RBC_MIXED ? 1024 : 512))
-    return "Nx too large for the x-pass LDS (<= 1024 mixed, <= 512 FP64)";
+  // the x-pass keeps three padded rows of complex values in LDS
+  if (p->Nx > 2048) return "Nx must be <= 2048";
   if (p->Nx_c > p->Nx || p->Nz_c > p->Nz) return "coarse grid must not exceed the fine grid";
   if (p->n_slices < 1) return "n_slices must be >= 1";
   if (!(p->t_end > p->t0)) return "t_end must exceed t0";

@@ -42,6 +42,7 @@ struct GridDev {
   int Nx, Nz, Mx, Px, Pz, n;      // n = Nz / 2
   int nrT, nrP;                   // band rows per parity: n - 1 (T, u_bar), n - 2 (psi)
   int MT;                         // modes per block in the per-mode kernel
+  int ntile;                      // ceil(Mx / MT): mode tiles (mixed-space arrays are tile-major)
   int state;                      // doubles per state = 4 Mx Nz
   double kscale;                  // k_m = m * kscale
   double nu, kappa, scale;        // viscosity, diffusivity, dzeta/dz = 2/Lz
@@ -88,8 +89,8 @@ size_t plan_device_bytes(const GridPlan& g);
 // Per-grid work buffers for a batch of `cap` slices.
 struct Work {
   int cap = 0;
-  void* Q = nullptr;       // Real [cap][6][Pz][Mx][2]
-  void* Nh = nullptr;      // Real [cap][2][Pz][Mx][2]
+  void* Q = nullptr;       // Real [cap][6][ntile][Pz][MT][2]
+  void* Nh = nullptr;      // Real [cap][2][ntile][Pz][MT][2]
   void* qbar = nullptr;    // Real [cap][Pz]
   void* Ehist = nullptr;   // Real [s][cap][state]
   double* LYhist = nullptr;  // [s-1][cap][state]

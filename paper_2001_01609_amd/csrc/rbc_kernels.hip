@@ -44,70 +44,126 @@ __device__ __forceinline__ Cx<Real> csub(Cx<Real> a, Cx<Real> b) { return {a.x -
 
 // ------------------------------------------------------------------ x-pass ---
 
-// One Stockham radix-R pass (Bainville's autosort form) over `cnt` signals
-// of length N stored with stride N, with P = product of the radices already
-// applied: out[j + q P] = DFT_R over in[i + r N/R] twiddled by
-// exp(sign 2 pi i r k / (P R)), k = i mod P, j = (i - k) R + k.  The radix
-// plan is 4, ..., 4, (2), 3, so P is a power of two in every pass and
-// r k N/(P R) < N indexes the twiddle table directly.
-template <typename Real, int R, int N, int P>
-__device__ __forceinline__ void stockham_pass(const Cx<Real>* __restrict__ in, Cx<Real>* __restrict__ out,
-                                              const Cx<Real>* __restrict__ tw, int cnt, Real sign) {
-  constexpr int T = N / R;
-  constexpr int TS = N / (P * R);
-  for (int c = 0; c < cnt; ++c) {
-    const Cx<Real>* x = in + c * N;
-    Cx<Real>* y = out + c * N;
-    for (int i = threadIdx.x; i < T; i += kBlock) {
-      const int k = i & (P - 1);
-      Cx<Real> a[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        Cx<Real> v = x[i + r * T];
-        if (r > 0 && P > 1) {
-          Cx<Real> t = tw[r * k * TS];
-          t.y *= -sign;   // table holds exp(-2 pi i t/N); the inverse uses the conjugate
-          v = cmul(v, t);
-        }
-        a[r] = v;
-      }
-      const int j = (i - k) * R + k;
-      if constexpr (R == 2) {
-        y[j] = cadd(a[0], a[1]);
-        y[j + P] = csub(a[0], a[1]);
-      } else if constexpr (R == 3) {
-        const Real h = Real(0.86602540378443864676);  // sqrt(3)/2
-        Cx<Real> t = cadd(a[1], a[2]), d = csub(a[1], a[2]);
-        Cx<Real> m = {a[0].x - Real(0.5) * t.x, a[0].y - Real(0.5) * t.y};
-        Cx<Real> id = {-sign * h * d.y, sign * h * d.x};   // sign * i * h * d
-        y[j] = cadd(a[0], t);
-        y[j + P] = cadd(m, id);
-        y[j + 2 * P] = csub(m, id);
-      } else {
-        Cx<Real> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
-        Cx<Real> s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
-        Cx<Real> id13 = {-sign * d13.y, sign * d13.x};      // sign * i * (a1 - a3)
-        y[j] = cadd(s02, s13);
-        y[j + P] = cadd(d02, id13);
-        y[j + 2 * P] = csub(s02, s13);
-        y[j + 3 * P] = csub(d02, id13);
-      }
-    }
+// Radix-4 DFT with sign s (exp(s 2 pi i / 4) = s i).
+template <typename Real>
+__device__ __forceinline__ void dft4(Cx<Real> a0, Cx<Real> a1, Cx<Real> a2, Cx<Real> a3, Real sign,
+                                     Cx<Real>* y) {
+  const Cx<Real> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  const Cx<Real> s13 = cadd(a1, a3), d13 = csub(a1, a3);
+  const Cx<Real> id13 = {-sign * d13.y, sign * d13.x};   // s i (a1 - a3)
+  y[0] = cadd(s02, s13);
+  y[1] = cadd(d02, id13);
+  y[2] = csub(s02, s13);
+  y[3] = csub(d02, id13);
+}
+
+// DFT_R of a[0..R-1] with sign s into y[0..R-1], R = 2, 3, 4 or 8.
+template <typename Real, int R>
+__device__ __forceinline__ void dft_small(const Cx<Real>* a, Real sign, Cx<Real>* y) {
+  if constexpr (R == 2) {
+    y[0] = cadd(a[0], a[1]);
+    y[1] = csub(a[0], a[1]);
+  } else if constexpr (R == 3) {
+    const Real h = Real(0.86602540378443864676);  // sqrt(3)/2
+    const Cx<Real> t = cadd(a[1], a[2]), d = csub(a[1], a[2]);
+    const Cx<Real> m = {a[0].x - Real(0.5) * t.x, a[0].y - Real(0.5) * t.y};
+    const Cx<Real> id = {-sign * h * d.y, sign * h * d.x};   // s i h d
+    y[0] = cadd(a[0], t);
+    y[1] = cadd(m, id);
+    y[2] = csub(m, id);
+  } else if constexpr (R == 4) {
+    dft4(a[0], a[1], a[2], a[3], sign, y);
+  } else {
+    // 8 = 2 x 4: even and odd DFT4s joined with exp(s 2 pi i q / 8)
+    Cx<Real> e[4], o[4];
+    dft4(a[0], a[2], a[4], a[6], sign, e);
+    dft4(a[1], a[3], a[5], a[7], sign, o);
+    const Real h = Real(0.70710678118654752440);   // sqrt(2)/2
+    const Cx<Real> w1 = {h * (o[1].x - sign * o[1].y), h * (o[1].y + sign * o[1].x)};
+    const Cx<Real> w2 = {-sign * o[2].y, sign * o[2].x};
+    const Cx<Real> w3 = {h * (-o[3].x - sign * o[3].y), h * (-o[3].y + sign * o[3].x)};
+    y[0] = cadd(e[0], o[0]);
+    y[4] = csub(e[0], o[0]);
+    y[1] = cadd(e[1], w1);
+    y[5] = csub(e[1], w1);
+    y[2] = cadd(e[2], w2);
+    y[6] = csub(e[2], w2);
+    y[3] = cadd(e[3], w3);
+    y[7] = csub(e[3], w3);
   }
 }
 
-// Radix plan for N = 3 * 2^q: fours, then a two if q is odd, then the three.
-// Returns the buffer holding the result.
-template <typename Real, int N, int P>
-__device__ Cx<Real>* fft_lds(Cx<Real>* a, Cx<Real>* b, const Cx<Real>* tw, int cnt, Real sign) {
+// In-place Stockham radix-R pass (Bainville's autosort form) over CNT
+// signals of length N (stride N) by one 64-lane wavefront: every lane first
+// gathers the inputs of its butterflies into registers, the block syncs,
+// then writes out[j + q P] = DFT_R over in[i + r N/R] twiddled by
+// exp(sign 2 pi i r k / (P R)), k = i mod P, j = (i - k) R + k.  The radix
+// plan is 8, ..., 8, (4 or 2), 3, so P is a power of two in every pass and
+// r k N/(P R) < N indexes the twiddle table directly; a butterfly's
+// twiddles serve all CNT signals.
+template <typename Real, int R, int N, int P, int CNT>
+__device__ __forceinline__ void stockham_pass(Cx<Real>* x, const Cx<Real>* __restrict__ tw, Real sign) {
+  constexpr int T = N / R;
+  constexpr int NB = (T + 63) / 64;
+  constexpr int TS = N / (P * R);
+  const int lane = threadIdx.x & 63;
+  Cx<Real> v[NB][CNT][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int i = lane + 64 * b;
+    if (i < T) {
+      const int k = i & (P - 1);
+      Cx<Real> t[R];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        if (P > 1) {
+          t[r] = tw[r * k * TS];
+          t[r].y *= -sign;   // table holds exp(-2 pi i t/N); the inverse uses the conjugate
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CNT; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const Cx<Real> u = x[c * N + i + r * T];
+          v[b][c][r] = (r > 0 && P > 1) ? cmul(u, t[r]) : u;
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int i = lane + 64 * b;
+    if (i >= T) continue;
+    const int k = i & (P - 1), j = (i - k) * R + k;
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+      Cx<Real> y[R];
+      dft_small<Real, R>(v[b][c], sign, y);
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[c * N + j + q * P] = y[q];
+    }
+  }
+  __syncthreads();
+}
+
+// Radix plan for N = 3 * 2^q: eights, then a four or a two, then the three.
+// CNT signals are transformed together while their butterflies fit in
+// registers, otherwise one at a time.
+template <typename Real, int N, int P, int CNT>
+__device__ __forceinline__ void fft_wave(Cx<Real>* x, const Cx<Real>* tw, Real sign) {
   constexpr int rem = N / P;
-  if constexpr (rem == 1) {
-    return a;
-  } else {
-    constexpr int R = (rem == 3) ? 3 : ((rem / 3) >= 4 ? 4 : 2);
-    stockham_pass<Real, R, N, P>(a, b, tw, cnt, sign);
-    __syncthreads();
-    return fft_lds<Real, N, P * R>(b, a, tw, cnt, sign);
+  if constexpr (rem > 1) {
+    constexpr int p2 = rem / 3;
+    constexpr int R = (rem == 3) ? 3 : (p2 >= 8 ? 8 : p2);
+    constexpr int regs = CNT * ((N / R + 63) / 64) * R * int(sizeof(Real)) / 2;   // 32-bit registers
+    if constexpr (regs <= 96) {
+      stockham_pass<Real, R, N, P, CNT>(x, tw, sign);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CNT; ++c) stockham_pass<Real, R, N, P, 1>(x + c * N, tw, sign);
+    }
+    fft_wave<Real, N, P * R, CNT>(x, tw, sign);
   }
 }
 
@@ -118,64 +174,66 @@ __device__ __forceinline__ Real wave_sum(Real v) {
   return v;
 }
 
-// One block per (slice, padded z point j).  Q holds the six fields of the
-// stage at the padded Gauss points, Fourier modes m < Mx; out: N_omega and
-// N_T modes m < Mx, and the horizontal mean of u w.
-template <typename Real, int PX>
-__global__ void __launch_bounds__(kBlock) xpass_kernel(GridDev g, const Real* __restrict__ Q,
-                                                       Real* __restrict__ Nh, Real* __restrict__ qbar) {
+// One block of RB wavefronts per (slice, group of RB padded z points); wave w
+// transforms row j = RB group + w.  Q holds the six fields of the stage at
+// the padded Gauss points and Nh receives N_omega and N_T, both mode-tile
+// major ([slice][quantity][tile][j][mode in tile][re, im]) so that a block
+// moves RB x MT contiguous values per tile; qbar gets the horizontal mean of
+// u w.
+template <typename Real, int PX, int RB>
+__global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* __restrict__ Q,
+                                                        Real* __restrict__ Nh, Real* __restrict__ qbar) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int Pz = g.Pz, Mx = g.Mx;
-  const int s = blockIdx.x / Pz, j = blockIdx.x - s * Pz;
-  Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem);   // [3][PX]
-  Cx<Real>* B = A + 3 * PX;                           // [3][PX]
-  Cx<Real>* tw = B + 3 * PX;                          // [PX] twiddles
-  Real* red = reinterpret_cast<Real*>(tw + PX);       // [kBlock / 64]
-  const Cx<Real>* gtw = reinterpret_cast<const Cx<Real>*>(g.tw);
-  const int tid = threadIdx.x;
+  const int Pz = g.Pz, Mx = g.Mx, MT = g.MT, ntile = g.ntile;
+  const int ngrp = Pz / RB;
+  const int s = blockIdx.x / ngrp, jg = blockIdx.x - s * ngrp;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = jg * RB + wv;
+  Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem) + wv * 3 * PX;   // this row's [3][PX]
+  const Cx<Real>* tw = reinterpret_cast<const Cx<Real>*>(g.tw);
+  const size_t tq = size_t(Pz) * MT;                 // complex values per (quantity, tile)
 
-  for (int t = tid; t < PX; t += kBlock) tw[t] = gtw[t];
   // the zero padding between the retained modes
-  const int nz0 = Mx, nzc = PX - 2 * Mx + 1;
+  const int nzc = PX - 2 * Mx + 1;
   for (int c = 0; c < 3; ++c)
-    for (int t = tid; t < nzc; t += kBlock) A[c * PX + nz0 + t] = {Real(0), Real(0)};
+    for (int t = lane; t < nzc; t += 64) A[c * PX + Mx + t] = {Real(0), Real(0)};
   // pack (u, w), (omega_x, omega_z), (T_x, T_z) into three complex spectra
-  const size_t rowQ = size_t(Mx) * 2;
-  const Cx<Real>* Qc = reinterpret_cast<const Cx<Real>*>(Q + (size_t(s) * 6 * Pz + j) * rowQ);
-  const size_t qs = size_t(Pz) * Mx;   // quantity stride in complex values
-  for (int c = 0; c < 3; ++c)
-    for (int m = tid; m < Mx; m += kBlock) {
-      const Cx<Real> qa = Qc[(2 * c) * qs + m], qb = Qc[(2 * c + 1) * qs + m];
+  const Cx<Real>* Qc = reinterpret_cast<const Cx<Real>*>(Q) + size_t(s) * 6 * ntile * tq + size_t(j) * MT;
+  for (int m = lane; m < Mx; m += 64) {
+    const int tile = m / MT, mt = m - tile * MT;
+    const Cx<Real>* q0 = Qc + size_t(tile) * tq + mt;
+    Cx<Real> q6[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) q6[c] = q0[size_t(c) * ntile * tq];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const Cx<Real> qa = q6[2 * c], qb = q6[2 * c + 1];
       A[c * PX + m] = {qa.x - qb.y, qa.y + qb.x};
       if (m > 0) A[c * PX + PX - m] = {qa.x + qb.y, qb.x - qa.y};
     }
+  }
   __syncthreads();
-  Cx<Real>* z = fft_lds<Real, PX, 1>(A, B, tw, 3, Real(1));
-  Cx<Real>* o = (z == A) ? B : A;
+  fft_wave<Real, PX, 1, 3>(A, tw, Real(1));
   Real uw = 0;
-  for (int t = tid; t < PX; t += kBlock) {
-    const Cx<Real> v1 = z[t], v2 = z[PX + t], v3 = z[2 * PX + t];
+  for (int t = lane; t < PX; t += 64) {
+    const Cx<Real> v1 = A[t], v2 = A[PX + t], v3 = A[2 * PX + t];
     const Real u = v1.x, w = v1.y;
-    o[t] = {u * v2.x + w * v2.y, u * v3.x + w * v3.y};
+    A[t] = {u * v2.x + w * v2.y, u * v3.x + w * v3.y};
     uw += u * w;
   }
   uw = wave_sum(uw);
-  if ((tid & 63) == 0) red[tid >> 6] = uw;
+  if (lane == 0) qbar[size_t(s) * Pz + j] = uw / Real(PX);
   __syncthreads();
-  if (tid == 0) {
-    Real tot = 0;
-    for (int wv = 0; wv < kBlock / 64; ++wv) tot += red[wv];
-    qbar[size_t(s) * Pz + j] = tot / Real(PX);
-  }
-  Cx<Real>* Z = fft_lds<Real, PX, 1>(o, z, tw, 1, Real(-1));
+  fft_wave<Real, PX, 1, 1>(A, tw, Real(-1));
   const Real inv2 = Real(0.5) / Real(PX);
-  Cx<Real>* out0 = reinterpret_cast<Cx<Real>*>(Nh + ((size_t(s) * 2 + 0) * Pz + j) * rowQ);
-  Cx<Real>* out1 = reinterpret_cast<Cx<Real>*>(Nh + ((size_t(s) * 2 + 1) * Pz + j) * rowQ);
-  for (int m = tid; m < Mx; m += kBlock) {
-    const Cx<Real> a = Z[m], b = Z[m == 0 ? 0 : PX - m];
+  Cx<Real>* out = reinterpret_cast<Cx<Real>*>(Nh) + size_t(s) * 2 * ntile * tq + size_t(j) * MT;
+  for (int m = lane; m < Mx; m += 64) {
+    const int tile = m / MT, mt = m - tile * MT;
+    const Cx<Real> a = A[m], b = A[m == 0 ? 0 : PX - m];
     // N_omega = (Z_m + conj Z_-m)/2, N_T = (Z_m - conj Z_-m)/(2i), both / PX
-    out0[m] = {(a.x + b.x) * inv2, (a.y - b.y) * inv2};
-    out1[m] = {(a.y + b.y) * inv2, (b.x - a.x) * inv2};
+    Cx<Real>* o = out + size_t(tile) * tq + mt;
+    o[0] = {(a.x + b.x) * inv2, (a.y - b.y) * inv2};
+    o[size_t(ntile) * tq] = {(a.y + b.y) * inv2, (b.x - a.x) * inv2};
   }
 }
 
@@ -380,7 +438,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   static_assert(kBlock % NZ == 0, "NZ must divide the block size");
   extern __shared__ __align__(16) unsigned char smem[];
   const int Mx = g.Mx;
-  const int ntile = (Mx + MT - 1) / MT;
+  const int ntile = g.ntile;   // ceil(Mx / MT)
   const int s = blockIdx.x / ntile, tile = blockIdx.x - s * ntile;
   const int m0 = tile * MT;
   const int st = g.state;
@@ -409,22 +467,21 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     }
     __syncthreads();
   } else {
-    // ---- phase A: products of this tile on the padded Gauss points, and
-    // the old state (eight loads in flight per thread)
-    const size_t rowQ = size_t(Mx) * 2;
+    // ---- phase A: products of this tile on the padded Gauss points (two
+    // contiguous runs of PZ x 2 MT values in the mode-tile-major layout), and
+    // the old state; eight loads in flight per thread
     {
       constexpr int U = 8;
-      constexpr int total = 4 * PZ * MT;
+      constexpr int half = PZ * 2 * MT, total = 2 * half;
+      const size_t tq = size_t(PZ) * 2 * MT;
+      const Real* n0 = Nh + (size_t(s) * 2 * ntile + tile) * tq;
+      const Real* n1 = n0 + size_t(ntile) * tq;
       for (int base = tid; base < total; base += kBlock * U) {
         Real v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int e = base + u * kBlock;
-          v[u] = Real(0);
-          if (e < total) {
-            const int c = e % (2 * MT), jq = e / (2 * MT);   // jq = qq * PZ + j
-            if (m0 + (c >> 1) < Mx) v[u] = Nh[(size_t(s) * 2 * PZ + jq) * rowQ + 2 * m0 + c];
-          }
+          v[u] = (e < half) ? n0[e] : ((e < total) ? n1[e - half] : Real(0));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -741,7 +798,6 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
     __syncthreads();
-    const size_t rowQ = size_t(Mx) * 2;
     for (int e = tid; e < PZ * MT; e += kBlock) {
       const int mt = e % MT, jj = e / MT, m = m0 + mt;
       if (m >= Mx) continue;
@@ -767,7 +823,8 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        Cx<Real>* d = reinterpret_cast<Cx<Real>*>(Q + ((size_t(s) * 6 + q) * PZ + jj) * rowQ) + m;
+        Cx<Real>* d = reinterpret_cast<Cx<Real>*>(Q) + ((size_t(s) * 6 + q) * ntile + tile) * (PZ * MT) +
+                      jj * MT + mt;
         *d = {out[q][0], out[q][1]};
       }
     }
@@ -776,7 +833,6 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   // wider tiles: item (j < PZ/2, mode) computes all six products and
   // quantities at j and PZ-1-j directly (fewer map loads per column)
   const Real* Wi = reinterpret_cast<const Real*>(g.Winv);
-  const size_t rowQ = size_t(Mx) * 2;
   for (int e = tid; e < PH * MT; e += kBlock) {
     const int mt = e % MT, j = e / MT, m = m0 + mt;
     if (m >= Mx) continue;
@@ -842,7 +898,8 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        Cx<Real>* d = reinterpret_cast<Cx<Real>*>(Q + ((size_t(s) * 6 + q) * PZ + jj) * rowQ) + m;
+        Cx<Real>* d = reinterpret_cast<Cx<Real>*>(Q) + ((size_t(s) * 6 + q) * ntile + tile) * (PZ * MT) +
+                      jj * MT + mt;
         *d = {out[q][0], out[q][1]};
       }
     }
@@ -1027,12 +1084,28 @@ hipError_t run_stage(const GridPlan& g, Work& w, const StageArgs& a, double* X, 
   }
 }
 
+// Rows per x-pass block: as many (up to four) as fit in 80 KiB of LDS.
+template <typename Real, int PX>
+constexpr int xpass_rows() {
+  constexpr size_t row = sizeof(Real) * 2 * 3 * size_t(PX);
+  return (4 * row <= 80 * 1024) ? 4 : ((2 * row <= 80 * 1024) ? 2 : 1);
+}
+
 template <typename Real, int PX>
 hipError_t run_xpass_t(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
   const GridDev& d = g.dev;
-  const size_t lds = sizeof(Real) * 2 * 7 * size_t(PX) + sizeof(Real) * (kBlock / 64);
-  hipLaunchKernelGGL((xpass_kernel<Real, PX>), dim3(n_slices * d.Pz), dim3(kBlock), lds, st, d, (const Real*)w.Q,
-                     (Real*)w.Nh, (Real*)w.qbar);
+  constexpr int RB = xpass_rows<Real, PX>();
+  // a small batch (the single-slice coarse sweep) would leave most CUs idle
+  // with several rows per block: one row per block there
+  if (RB > 1 && n_slices * (d.Pz / RB) < 256) {
+    const size_t lds = sizeof(Real) * 2 * 3 * size_t(PX);
+    hipLaunchKernelGGL((xpass_kernel<Real, PX, 1>), dim3(n_slices * d.Pz), dim3(64), lds, st, d, (const Real*)w.Q,
+                       (Real*)w.Nh, (Real*)w.qbar);
+  } else {
+    const size_t lds = sizeof(Real) * 2 * 3 * size_t(PX) * RB;
+    hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(n_slices * (d.Pz / RB)), dim3(64 * RB), lds, st, d,
+                       (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar);
+  }
   return hipGetLastError();
 }
 

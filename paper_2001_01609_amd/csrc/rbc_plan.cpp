@@ -18,7 +18,7 @@
 // R = [R1 | R2] and R2 square banded (b sub-, w-b super-diagonals),
 //   x = R2^-1 f,  V = R2^-1 R1,  y_head = (C1 - C2 V)^-1 (g - C2 x),
 //   y_tail = x - V y_head.
-// R2 is factored without pivoting; build_factors() checks the growth.
+// R2 is factored without pivoting; factor_bordered() reports the growth.
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -395,6 +395,7 @@ hipError_t upload_plan(GridPlan& g) {
   GridDev& d = g.dev;
   d.Nx = g.Nx; d.Nz = g.Nz; d.Mx = g.Mx; d.Px = g.Px; d.Pz = g.Pz; d.n = g.Nz / 2;
   d.nrT = d.n - 1; d.nrP = d.n - 2; d.MT = g.MT;
+  d.ntile = (g.Mx + g.MT - 1) / g.MT;
   d.state = 4 * g.Mx * g.Nz;
   d.kscale = 2.0 * M_PI / g.Lx;
   d.nu = g.nu; d.kappa = g.kappa; d.scale = g.scale; d.Lz = g.Lz;
@@ -414,11 +415,14 @@ hipError_t upload_plan(GridPlan& g) {
   return hipSuccess;
 }
 
+// Modes rounded up to whole tiles (the mixed-space arrays are tile-major).
+static size_t padded_modes(const GridPlan& g) { return size_t((g.Mx + g.MT - 1) / g.MT) * g.MT; }
+
 size_t work_bytes(const GridPlan& g, int cap) {
   size_t rb = g.mixed ? 4 : 8;
   size_t st = size_t(4) * g.Mx * g.Nz;
-  size_t q = size_t(cap) * 6 * g.Pz * g.Mx * 2 * rb;
-  size_t nh = size_t(cap) * 2 * g.Pz * g.Mx * 2 * rb + size_t(cap) * g.Pz * rb;
+  size_t q = size_t(cap) * 6 * g.Pz * padded_modes(g) * 2 * rb;
+  size_t nh = size_t(cap) * 2 * g.Pz * padded_modes(g) * 2 * rb + size_t(cap) * g.Pz * rb;
   size_t eh = size_t(g.tab.s) * cap * st * rb;
   size_t ly = size_t(g.tab.s - 1) * cap * st * 8;
   return q + nh + eh + ly + 4 * 256;
@@ -429,8 +433,8 @@ hipError_t alloc_work(const GridPlan& g, int cap, Work& w) {
   size_t st = size_t(4) * g.Mx * g.Nz;
   w.cap = cap;
   hipError_t e;
-  if ((e = hipMalloc(&w.Q, size_t(cap) * 6 * g.Pz * g.Mx * 2 * rb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&w.Nh, size_t(cap) * 2 * g.Pz * g.Mx * 2 * rb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.Q, size_t(cap) * 6 * g.Pz * padded_modes(g) * 2 * rb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&w.Nh, size_t(cap) * 2 * g.Pz * padded_modes(g) * 2 * rb)) != hipSuccess) return e;
   if ((e = hipMalloc(&w.qbar, size_t(cap) * g.Pz * rb)) != hipSuccess) return e;
   if ((e = hipMalloc(&w.Ehist, size_t(g.tab.s) * cap * st * rb)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.LYhist, size_t(g.tab.s - 1) * cap * st * 8)) != hipSuccess) return e;

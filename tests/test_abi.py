@@ -65,7 +65,7 @@ def test_argument_validation_without_device():
     from paper_2001_01609_amd import rbc as R
     p = R.rbc_default_params()
     assert R.rbc_query_footprint(p) > 0
-    bad = [("Nx", 48), ("Nz", 7), ("Nz", 4), ("Nz", 24), ("Nz", 512), ("Nx", 2048), ("Nx_c", 128), ("n_slices", 0), ("scheme_f", 3),
+    bad = [("Nx", 48), ("Nz", 7), ("Nz", 4), ("Nz", 24), ("Nz", 512), ("Nx", 4096), ("Nx_c", 128), ("n_slices", 0), ("scheme_f", 3),
            ("precision", 7), ("dt_f", 0.0), ("t_end", -1.0)]
     for field, val in bad:
         q = R.rbc_default_params()
