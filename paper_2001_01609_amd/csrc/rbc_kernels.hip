@@ -367,6 +367,111 @@ __device__ __forceinline__ void solve_P_format(double* __restrict__ v, int p, co
   }
 }
 
+// Scan form of the same bordered solves: one lane per band row, W lanes per
+// system (W = power of two > NR, segments aligned to W).  Each elimination
+// sweep is a linear recurrence, i.e. the composition of one affine map per
+// row, evaluated as an inclusive Hillis-Steele scan with lane shuffles
+// (log2 W steps instead of NR); the wall-row sums are segment reductions.
+// li = lane within the segment; every lane of a segment must call.
+template <int W>
+__device__ __forceinline__ double seg_sum(double x) {
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+
+template <int NR, int W>
+__device__ __forceinline__ void solve_T_scan(double* __restrict__ v, int p, const double* __restrict__ fac,
+                                             double gbc, int li) {
+  const bool act = li < NR;
+  const double* fr = fac + li * kFacT;
+  const double f = act ? v[2 * li + p] : 0.0;
+  const double l = act ? fr[0] : 0.0;          // l_0 = 0
+  const double d = act ? fr[1] : 0.0;
+  const double u = act ? fr[2] : 0.0;          // u_(NR-1) = 0
+  const double vc = act ? fr[3] : 0.0;
+  // forward: y_i = -l_i y_(i-1) + f_i
+  double A = -l, B = f;
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double Ap = __shfl_up(A, o, W), Bp = __shfl_up(B, o, W);
+    if (li >= o) {
+      B = A * Bp + B;
+      A = A * Ap;
+    }
+  }
+  // backward: x_i = (-u_i d_i) x_(i+1) + d_i y_i   (rows >= NR contribute 0)
+  A = -u * d;
+  B = d * B;
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double An = __shfl_down(A, o, W), Bn = __shfl_down(B, o, W);
+    if (li + o < W) {
+      B = A * Bn + B;
+      A = A * An;
+    }
+  }
+  const double sum = seg_sum<W>(B);
+  const double xh = fac[NR * kFacT] * (gbc - sum);
+  if (act) v[2 * (li + 1) + p] = B - vc * xh;
+  if (li == 0) v[p] = xh;
+}
+
+template <int NR, int W>
+__device__ __forceinline__ void solve_P_scan(double* __restrict__ v, int p, const double* __restrict__ fac, int li) {
+  const bool act = li < NR;
+  const double* fr = fac + li * kFacP;
+  const double f = act ? v[2 * li + p] : 0.0;
+  // forward: (y_i, y_(i-1)) = [[-l1, -l2], [1, 0]] (y_(i-1), y_(i-2)) + (f_i, 0)
+  double m00 = act ? -fr[0] : 0.0, m01 = act ? -fr[1] : 0.0, m10 = act ? 1.0 : 0.0, m11 = 0.0;
+  double c0 = f, c1 = 0.0;
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double p00 = __shfl_up(m00, o, W), p01 = __shfl_up(m01, o, W);
+    const double p10 = __shfl_up(m10, o, W), p11 = __shfl_up(m11, o, W);
+    const double q0 = __shfl_up(c0, o, W), q1 = __shfl_up(c1, o, W);
+    if (li >= o) {   // this composite after the earlier one
+      const double n0 = m00 * q0 + m01 * q1 + c0, n1 = m10 * q0 + m11 * q1 + c1;
+      const double a00 = m00 * p00 + m01 * p10, a01 = m00 * p01 + m01 * p11;
+      const double a10 = m10 * p00 + m11 * p10, a11 = m10 * p01 + m11 * p11;
+      m00 = a00; m01 = a01; m10 = a10; m11 = a11;
+      c0 = n0; c1 = n1;
+    }
+  }
+  const double y = c0;
+  // backward: (x_i, x_(i+1)) = [[-u1 d, -u2 d], [1, 0]] (x_(i+1), x_(i+2)) + (d y_i, 0)
+  const double dd = act ? fr[2] : 0.0;
+  m00 = act ? -fr[3] * dd : 0.0; m01 = act ? -fr[4] * dd : 0.0; m10 = act ? 1.0 : 0.0; m11 = 0.0;
+  c0 = dd * y; c1 = 0.0;
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double p00 = __shfl_down(m00, o, W), p01 = __shfl_down(m01, o, W);
+    const double p10 = __shfl_down(m10, o, W), p11 = __shfl_down(m11, o, W);
+    const double q0 = __shfl_down(c0, o, W), q1 = __shfl_down(c1, o, W);
+    if (li + o < W) {   // this row's map after the later rows' composite
+      const double n0 = m00 * q0 + m01 * q1 + c0, n1 = m10 * q0 + m11 * q1 + c1;
+      const double a00 = m00 * p00 + m01 * p10, a01 = m00 * p01 + m01 * p11;
+      const double a10 = m10 * p00 + m11 * p10, a11 = m10 * p01 + m11 * p11;
+      m00 = a00; m01 = a01; m10 = a10; m11 = a11;
+      c0 = n0; c1 = n1;
+    }
+  }
+  const double x = c0;
+  const double nn = double(2 * (li + 2) + p);
+  const double s0 = seg_sum<W>(x), s1 = seg_sum<W>(act ? nn * nn * x : 0.0);
+  const double* si = fac + NR * kFacP;
+  const double h0 = -(si[0] * s0 + si[1] * s1);
+  const double h1 = -(si[2] * s0 + si[3] * s1);
+  if (act) v[2 * (li + 2) + p] = x - fr[5] * h0 - fr[6] * h1;
+  if (li == 0) {
+    v[p] = h0;
+    v[2 + p] = h1;
+  }
+}
+
+// Smallest power of two above n (segment width of the scan solves).
+constexpr int seg_width(int n) { return n < 4 ? 4 : (n < 8 ? 8 : (n < 16 ? 16 : (n < 32 ? 32 : 64))); }
+
 // Copies the factor blocks of modes m0..m0+MT-1 (both parities) into LDS,
 // eight loads in flight per thread.
 template <int MT>
@@ -655,14 +760,31 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
     __syncthreads();
-    // ---- phase D: temperature solves, lanes (mode, parity, re/im)
-    if (tid < 4 * MT) {
+    // ---- phase D: temperature solves of the systems (mode, parity, re/im).
+    // Two-mode tiles (latency-bound launches): scans with one lane per band
+    // row up to 63 rows.  Wider tiles (throughput-bound batched launches,
+    // where the other blocks' phases hide the sweep): one lane per system.
+    if constexpr (kWide && NRT < 64) {
+      constexpr int WS = seg_width(NRT);
+      for (int sys0 = 0; sys0 < 4 * MT; sys0 += kBlock / WS) {
+        const int sys = sys0 + tid / WS, li = tid % WS;
+        if (sys < 4 * MT) {
+          const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
+          if (m < Mx) {
+            double gbc = 0.0;
+            if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
+            solve_T_scan<NRT, WS>(sY + ((MT + mt) * 2 + ri) * LD, p,
+                                  sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc, li);
+          }
+        }
+      }
+    } else if (tid < 4 * MT) {
       const int mt = tid >> 2, p = (tid >> 1) & 1, ri = tid & 1, m = m0 + mt;
       if (m < Mx) {
         double gbc = 0.0;
         if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
         solve_T_format<NRT, kWide>(sY + ((MT + mt) * 2 + ri) * LD, p,
-                            sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc);
+                                   sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc);
       }
     }
     __syncthreads();
@@ -685,7 +807,23 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
     __syncthreads();
-    if (tid < 4 * MT) {
+    if constexpr (kWide && NRT < 64) {
+      constexpr int WS = seg_width(NRT);   // NRP < NRT: the same segments fit
+      for (int sys0 = 0; sys0 < 4 * MT; sys0 += kBlock / WS) {
+        const int sys = sys0 + tid / WS, li = tid % WS;
+        if (sys < 4 * MT) {
+          const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
+          if (m < Mx) {
+            const double* fac = sF + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
+            double* v = sY + (mt * 2 + ri) * LD;
+            if (m == 0)
+              solve_T_scan<NRT, WS>(v, p, fac, 0.0, li);
+            else
+              solve_P_scan<NRP, WS>(v, p, fac, li);
+          }
+        }
+      }
+    } else if (tid < 4 * MT) {
       const int mt = tid >> 2, p = (tid >> 1) & 1, ri = tid & 1, m = m0 + mt;
       if (m < Mx) {
         const double* fac = sF + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
