@@ -110,6 +110,62 @@ def cpu_baseline(w, seconds: float):
                       f"from the seeded initial state; {el:.1f} s on one thread"}
 
 
+def time_to_solution(w, tol: float = 1e-8):
+    """Parareal (this workload's precision, all slices batched) to a defect
+    <= tol, against the serial FP64 fine stepper on one run over the same
+    horizon and fine step.  Both report time-averaged Nusselt numbers over the
+    whole horizon (samples every NU_STRIDE fine steps)."""
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev).cuda_stream
+    S = w.n_slices
+    # Parareal
+    p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0)
+    h = R.rbc_create(p, st)
+    try:
+        n = R.rbc_state_size(h, 0)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
+        R.rbc_init_state(h, w.seed, w.noise_amp, U)
+        torch.cuda.synchronize()
+        print("[bench] time to solution: Parareal", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        status, kd, defects, nu = R.parareal_iterate(h, U, S, tol, want_nu=True)
+        torch.cuda.synchronize()
+        t_para = time.perf_counter() - t0
+        u_end = U[S * n:].clone()
+    finally:
+        R.rbc_destroy(h)
+    # serial FP64 stepper: one run over the whole horizon
+    q = R.params_from_workload(w, n_slices=1, precision=R.RBC_FP64, nu_stride=NU_STRIDE, nu_t_start=w.t0)
+    q.dt_f = (w.t_end - w.t0) / S / math.ceil((w.t_end - w.t0) / S / w.dt_f - 1e-9)   # the Parareal fine step
+    q.dt_c = q.dt_f
+    h = R.rbc_create(q, st)
+    try:
+        ns, dts = R.rbc_steps_per_slice(h, 0)
+        V = torch.zeros(n, dtype=torch.float64, device=dev)
+        R.rbc_init_state(h, w.seed, w.noise_amp, V)
+        nus = torch.zeros((ns // NU_STRIDE) * 3, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        print(f"[bench] time to solution: serial FP64 ({ns} steps)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        R.rbc_fine_step_batch(h, V, V, 1, ns, nus)
+        torch.cuda.synchronize()
+        t_ser = time.perf_counter() - t0
+        nu_ser = nus.view(-1, 3).mean(0).cpu().numpy()
+        rel = float(torch.linalg.norm(u_end - V) / torch.linalg.norm(V))
+    finally:
+        R.rbc_destroy(h)
+    nu_par = nu[-1]
+    return {"parareal_s": t_para, "serial_fp64_s": t_ser, "speedup": t_ser / t_para,
+            "iterations": kd, "status": status, "tol": tol, "defects": [float(d) for d in defects],
+            "serial_steps": ns, "nu_avg_parareal": [float(v) for v in nu_par],
+            "nu_avg_serial_fp64": [float(v) for v in nu_ser],
+            "nu_V_rel_diff": float(abs(nu_par[0] - nu_ser[0]) / abs(nu_ser[0])),
+            "final_state_rel_l2_vs_serial_fp64": rel}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +173,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=I.C2.name, choices=sorted(I.WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample length (0 = skip)")
+    ap.add_argument("--no-tts", action="store_true",
+                    help="skip the Parareal vs serial FP64 time-to-solution comparison")
     ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
                     help="counter-collection mode: only N batched fine steps (same kernels and launch "
                          "shapes as the timed run), no Parareal iteration, no JSON line")
@@ -237,6 +295,8 @@ def main() -> int:
         "parareal": {"defects": defects, "nu_mean_last": [float(v) for v in nu_host.reshape(-1, 3).mean(0)],
                      "finite": finite},
     }
+    if not args.no_tts:
+        out["time_to_solution"] = time_to_solution(w)
     if args.cpu_seconds > 0:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         cb = cpu_baseline(w, args.cpu_seconds)

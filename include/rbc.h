@@ -81,6 +81,13 @@ typedef struct {
   int32_t nu_stride;       /* sample Nu every nu_stride fine steps; 0 = off */
   double nu_t_start;       /* start of the Nu time-average window           */
   double T_bot, T_top;     /* wall temperatures at z = 0 and z = Lz (Eq. 4) */
+  int32_t promote_fp64;    /* RBC_MIXED only: 1 = when parareal_iterate's
+                              defect would meet the FP32 rounding floor
+                              (near 1e-7): after iteration k >= 2, still
+                              above tol, if tol < 1e-6 and the defect is
+                              <= 1e-3, or if the defect stalls (<= 1e-4 and
+                              more than half the previous one), later fine
+                              and coarse sweeps run all-FP64.  Default 1.  */
 } rbc_params;
 
 /* Fill p with defaults (T_bot = 1, T_top = 0, ARS443, FP64, no sampling). */
@@ -153,6 +160,10 @@ rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first_slice,
 rbc_status parareal_iterate(rbc_handle h, double* U_dev, int32_t k_max, double tol,
                             int32_t* k_done_host, double* defect_hist_host,
                             double* nu_avg_hist_host);
+
+/* Iteration from which the last parareal_iterate ran its fine and coarse
+ * sweeps in FP64 (promote_fp64), 0 if it never promoted. */
+rbc_status rbc_fine_fp64_from(rbc_handle h, int32_t* k_host);
 
 /* Nusselt numbers of section 2.2 for n_states fine states (Eqs. 8-10):
  * nu_host[i] = (Nu_V, Nu_b, Nu_t).  Nu_b, Nu_t: -dT/dz of the horizontal

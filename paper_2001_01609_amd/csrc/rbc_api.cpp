@@ -16,7 +16,10 @@ struct rbc_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   rbc::GridPlan fine, coarse;
-  rbc::Work wf, wc;
+  rbc::GridPlan fine64, coarse64;   // all-FP64 plans for promoted sweeps (mixed + promote_fp64)
+  bool has64 = false;
+  int k_fp64 = 0;              // iteration the last parareal_iterate promoted at (0: never)
+  rbc::Work wf, wc, wf64, wc64;
   int nf = 0, nc = 0;          // steps per slice
   double* Xc = nullptr;        // coarse state being advanced
   double* Fbuf = nullptr;      // [S][state]   F(U_n^(k-1))
@@ -92,8 +95,9 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.scheme = coarse ? p->scheme_c : p->scheme_f;
   g.mixed = (p->precision == RBC_MIXED);
   // modes per block of the per-mode kernel (2, 4, 6 or 8); RBC_MODE_TILE overrides
-  // (the single-slice coarse grid is latency-bound: small tiles, more blocks)
-  g.MT = (coarse || g.Nz >= 128) ? 2 : 4;
+  // (the single-slice coarse grid and single-run fine batches are latency-bound:
+  // small tiles, more blocks)
+  g.MT = (coarse || g.Nz >= 128 || p->n_slices <= 2) ? 2 : 4;
   if (const char* e = std::getenv("RBC_MODE_TILE")) {
     const int v = std::atoi(e);
     if (v == 2 || v == 4 || v == 6 || v == 8) g.MT = v;
@@ -128,6 +132,10 @@ void release(rbc_handle h) {
   h->timing.ev.clear();
   rbc::free_work(h->wf);
   rbc::free_work(h->wc);
+  rbc::free_work(h->wf64);
+  rbc::free_work(h->wc64);
+  if (h->fine64.d_tables) (void)hipFree(h->fine64.d_tables);
+  if (h->coarse64.d_tables) (void)hipFree(h->coarse64.d_tables);
   for (void* q : {(void*)h->Xc, (void*)h->Fbuf, (void*)h->Gbuf, (void*)h->part, (void*)h->dscal,
                   (void*)h->nu_f, (void*)h->nu_c, h->fine.d_tables, h->coarse.d_tables})
     if (q) (void)hipFree(q);
@@ -161,6 +169,7 @@ rbc_status rbc_default_params(rbc_params* p) {
   p->precision = RBC_FP64;
   p->nu_stride = 0; p->nu_t_start = 0;
   p->T_bot = 1; p->T_top = 0;
+  p->promote_fp64 = 1;
   return RBC_OK;
 }
 
@@ -187,6 +196,11 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes) {
   sampling(p, nf, nc, dtf, dtc, &nsf, &nsc, &sc);
   *device_bytes = tables(f) + tables(c) + rbc::work_bytes(f, p->n_slices) + rbc::work_bytes(c, 1) +
                   pararea_bytes(p, f, c, nsf, nsc);
+  if (p->precision == RBC_MIXED && p->promote_fp64) {
+    rbc::GridPlan f64 = f, c64 = c;
+    f64.mixed = c64.mixed = false;
+    *device_bytes += tables(f64) + rbc::work_bytes(f64, p->n_slices) + tables(c64) + rbc::work_bytes(c64, 1);
+  }
   return RBC_OK;
 }
 
@@ -206,6 +220,14 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
   setup_grid(h->coarse, p, true, dtc);
   e = rbc::build_plan(h->fine);
   if (e.empty()) e = rbc::build_plan(h->coarse);
+  h->has64 = (p->precision == RBC_MIXED && p->promote_fp64 != 0);
+  if (e.empty() && h->has64) {
+    setup_grid(h->fine64, p, false, dtf);
+    setup_grid(h->coarse64, p, true, dtc);
+    h->fine64.mixed = h->coarse64.mixed = false;
+    e = rbc::build_plan(h->fine64);
+    if (e.empty()) e = rbc::build_plan(h->coarse64);
+  }
   if (!e.empty()) {
     delete h;
     return fail(nullptr, RBC_ERR_STATE, e);
@@ -218,8 +240,13 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
     return fail(nullptr, st, m);
   };
   if (he != hipSuccess) return bail(RBC_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
-  if ((he = rbc::upload_plan(h->fine)) != hipSuccess || (he = rbc::upload_plan(h->coarse)) != hipSuccess)
+  if ((he = rbc::upload_plan(h->fine)) != hipSuccess || (he = rbc::upload_plan(h->coarse)) != hipSuccess ||
+      (h->has64 && ((he = rbc::upload_plan(h->fine64)) != hipSuccess ||
+                    (he = rbc::upload_plan(h->coarse64)) != hipSuccess)))
     return bail(RBC_ERR_OOM, std::string("table upload: ") + hipGetErrorString(he));
+  if (h->has64 && ((he = rbc::alloc_work(h->fine64, p->n_slices, h->wf64)) != hipSuccess ||
+                   (he = rbc::alloc_work(h->coarse64, 1, h->wc64)) != hipSuccess))
+    return bail(RBC_ERR_OOM, std::string("workspace: ") + hipGetErrorString(he));
   if ((he = rbc::alloc_work(h->fine, p->n_slices, h->wf)) != hipSuccess ||
       (he = rbc::alloc_work(h->coarse, 1, h->wc)) != hipSuccess)
     return bail(RBC_ERR_OOM, std::string("workspace: ") + hipGetErrorString(he));
@@ -337,13 +364,16 @@ namespace {
 
 // Coarse sweep over slices [first, S): see rbc_coarse_sweep.  Coarse Nu
 // samples of slice n go to nu_c[n] when requested.
-rbc_status sweep(rbc_handle h, int mode, int first, double* U, const double* F, double* G, bool with_nu) {
+rbc_status sweep(rbc_handle h, int mode, int first, double* U, const double* F, double* G, bool with_nu,
+                 bool use64 = false) {
   const int S = h->p.n_slices;
   const size_t fs = h->fine.dev.state, cs = h->coarse.dev.state;
+  rbc::GridPlan& cp = use64 ? h->coarse64 : h->coarse;
+  rbc::Work& cw = use64 ? h->wc64 : h->wc;
   for (int n = first; n < S; ++n) {
-    HIPCHK(h, rbc::launch_restrict(h->fine, h->coarse, U + n * fs, h->Xc, h->stream));
+    HIPCHK(h, rbc::launch_restrict(h->fine, cp, U + n * fs, h->Xc, h->stream));
     double* nu = (with_nu && h->nu_c) ? h->nu_c + size_t(n) * h->nsc * 3 : nullptr;
-    HIPCHK(h, rbc::launch_steps(h->coarse, h->wc, h->Xc, 1, h->nc, nu, h->stride_c, h->nsc, h->stream));
+    HIPCHK(h, rbc::launch_steps(cp, cw, h->Xc, 1, h->nc, nu, h->stride_c, h->nsc, h->stream));
     HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, mode, U + (n + 1) * fs, mode == 1 ? F + n * fs : nullptr,
                                   h->Xc, G + n * cs, h->part + size_t(n + 1) * rbc::kCombineBlocks * 2,
                                   h->stream));
@@ -416,8 +446,10 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
       nu_hist[0] = nu_hist[1] = nu_hist[2] = NAN;
     }
   }
-  double defect = INFINITY;
+  double defect = INFINITY, prev = INFINITY;
   int k = 0;
+  bool f64 = false;
+  h->k_fp64 = 0;
   while (k < k_max && k < S) {
     ++k;
     // F on slices k-1..S-1 from U^(k-1)
@@ -425,12 +457,14 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
     double* nu = want_nu ? h->nu_f + size_t(k - 1) * h->nsf * 3 : nullptr;
     HIPCHK(h, hipMemcpyAsync(h->Fbuf + (k - 1) * fs, U + (k - 1) * fs, size_t(na) * fs * 8,
                              hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, rbc::launch_steps(h->fine, h->wf, h->Fbuf + (k - 1) * fs, na, h->nf, nu, h->p.nu_stride, h->nsf,
+    rbc::GridPlan& fp = f64 ? h->fine64 : h->fine;
+    rbc::Work& fw = f64 ? h->wf64 : h->wf;
+    HIPCHK(h, rbc::launch_steps(fp, fw, h->Fbuf + (k - 1) * fs, na, h->nf, nu, h->p.nu_stride, h->nsf,
                                 h->stream, &h->timing));
     // U_k^k = F(U_(k-1)^(k-1)) exactly; then the correction sweep
     HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, 2, U + k * fs, h->Fbuf + (k - 1) * fs, nullptr, nullptr,
                                   h->part + size_t(k) * rbc::kCombineBlocks * 2, h->stream));
-    if ((s = sweep(h, 1, k, U, h->Fbuf, h->Gbuf, false)) != RBC_OK) return s;
+    if ((s = sweep(h, 1, k, U, h->Fbuf, h->Gbuf, false, f64)) != RBC_OK) return s;
     bool bad = false;
     if ((s = read_defect(h, k, S + 1, &defect, &bad)) != RBC_OK) return s;
     defect_hist[k - 1] = defect;
@@ -439,8 +473,24 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
       return s;
     if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
     if (defect <= tol) break;
+    // The FP32 rounding of the mixed propagators sets a defect floor near
+    // 1e-7: for a tolerance below 1e-6 switch to FP64 once the iteration
+    // error is small (1e-3) but still far above the switch's own jump, or
+    // whenever the defect stalls below 1e-4.
+    if (h->has64 && !f64 && k >= 2 &&
+        ((tol < 1e-6 && defect <= 1e-3) || (defect <= 1e-4 && defect > 0.5 * prev))) {
+      f64 = true;
+      h->k_fp64 = k + 1;
+    }
+    prev = defect;
   }
   if (k < S && !(defect <= tol) && tol > 0) return RBC_NOT_CONVERGED;
+  return RBC_OK;
+}
+
+rbc_status rbc_fine_fp64_from(rbc_handle h, int32_t* k) {
+  if (!h || !k) return fail(h, RBC_ERR_ARG, "null argument");
+  *k = h->k_fp64;
   return RBC_OK;
 }
 

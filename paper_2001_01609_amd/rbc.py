@@ -49,6 +49,7 @@ class rbc_params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("nu_stride", ctypes.c_int32),
         ("nu_t_start", ctypes.c_double),
         ("T_bot", ctypes.c_double), ("T_top", ctypes.c_double),
+        ("promote_fp64", ctypes.c_int32),
     ]
 
 
@@ -71,6 +72,7 @@ def _load():
         "rbc_coarse_sweep": (st, [vp, i32, i32, vp, vp, vp, P(dbl)]),
         "parareal_iterate": (st, [vp, vp, i32, dbl, P(i32), P(dbl), P(dbl)]),
         "rbc_nusselt": (st, [vp, vp, i32, P(dbl)]),
+        "rbc_fine_fp64_from": (st, [vp, P(i32)]),
         "rbc_explicit_terms": (st, [vp, vp, vp]),
         "rbc_kernel_timing_enable": (st, [vp, i32, i32]),
         "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64)]),
@@ -167,6 +169,12 @@ def parareal_iterate(h, U, k_max: int, tol: float, want_nu: bool = False):
         nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_nu else None), h)
     kd = k.value
     return st, kd, defects[:kd].copy(), (nu[: kd + 1].copy() if want_nu else None)
+
+
+def rbc_fine_fp64_from(h) -> int:
+    k = ctypes.c_int32()
+    _check(_lib.rbc_fine_fp64_from(h, ctypes.byref(k)), h)
+    return k.value
 
 
 def rbc_nusselt(h, U, n_states: int) -> np.ndarray:

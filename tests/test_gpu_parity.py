@@ -283,6 +283,7 @@ def test_parareal_exact_on_first_k_slices_bitwise():
     """After k iterations slices 0..k equal the serial fine solve bitwise;
     at k = S the whole trajectory does (finite termination)."""
     p = _tiny_parareal_params(mixed=True)
+    p.promote_fp64 = 0          # the serial reference is the mixed propagator itself
     case("parareal finite termination, mixed")
     g = grid(p)
     U0 = O.initial_state(g, I.gaussian_noise(12, g.Nx, g.Nz), 0.3).pack()
@@ -372,3 +373,39 @@ def test_fullsize_batch_sampled_slices(w):
     tol = MIXED_TOL if w.mixed else FP64_TOL
     assert rel(got[0], st.run(X0, 2).pack()) < tol
     assert rel(got[31], st.run(X1, 2).pack()) < tol
+
+
+def test_parareal_promotes_stalled_mixed_fine_sweeps_to_fp64():
+    """Mixed precision: the defect stalls near the FP32 rounding level; with
+    promotion the later fine sweeps run in FP64, the defect reaches a
+    tolerance below that floor before finite termination, and the result
+    matches the serial all-FP64 fine solve."""
+    S, tol = 8, 1e-10
+    p = params(32, 16, Ra=5e4, dt=0.01, scheme=4, mixed=True, S=S, t_end=4.0, dt_c=0.04)
+    case("parareal FP64 promotion, 8 slices")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(21, g.Nx, g.Nz), 0.3).pack()
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        st, kd, defects, _ = R().parareal_iterate(h, U, S, tol)
+        kp = R().rbc_fine_fp64_from(h)
+        got = U.cpu().numpy().reshape(S + 1, -1)[S]
+    finally:
+        R().rbc_destroy(h)
+    assert 2 < kp <= kd, (kp, kd, defects)
+    assert kd < S and defects[-1] <= tol, defects
+    # serial all-FP64 reference over the whole horizon
+    q = params(32, 16, Ra=5e4, dt=0.01, scheme=4, mixed=False, S=S, t_end=4.0, dt_c=0.04)
+    h = create(q)
+    try:
+        nf, _ = R().rbc_steps_per_slice(h, 0)
+        V = to_dev(U0)
+        for _ in range(S):
+            R().rbc_fine_step_batch(h, V, V, 1, nf)
+        ref = V.cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    assert rel(got, ref) < 1e-8
