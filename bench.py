@@ -134,6 +134,7 @@ def time_to_solution(w, tol: float = 1e-8):
         status, kd, defects, nu = R.parareal_iterate(h, U, S, tol, want_nu=True)
         torch.cuda.synchronize()
         t_para = time.perf_counter() - t0
+        k64 = R.rbc_fine_fp64_from(h)
         u_end = U[S * n:].clone()
     finally:
         R.rbc_destroy(h)
@@ -159,7 +160,7 @@ def time_to_solution(w, tol: float = 1e-8):
         R.rbc_destroy(h)
     nu_par = nu[-1]
     return {"parareal_s": t_para, "serial_fp64_s": t_ser, "speedup": t_ser / t_para,
-            "iterations": kd, "status": status, "tol": tol, "defects": [float(d) for d in defects],
+            "iterations": kd, "fp64_from_iteration": k64, "status": status, "tol": tol, "defects": [float(d) for d in defects],
             "serial_steps": ns, "nu_avg_parareal": [float(v) for v in nu_par],
             "nu_avg_serial_fp64": [float(v) for v in nu_ser],
             "nu_V_rel_diff": float(abs(nu_par[0] - nu_ser[0]) / abs(nu_ser[0])),

@@ -81,13 +81,21 @@ typedef struct {
   int32_t nu_stride;       /* sample Nu every nu_stride fine steps; 0 = off */
   double nu_t_start;       /* start of the Nu time-average window           */
   double T_bot, T_top;     /* wall temperatures at z = 0 and z = Lz (Eq. 4) */
-  int32_t promote_fp64;    /* RBC_MIXED only: 1 = when parareal_iterate's
-                              defect would meet the FP32 rounding floor
-                              (near 1e-7): after iteration k >= 2, still
-                              above tol, if tol < 1e-6 and the defect is
-                              <= 1e-3, or if the defect stalls (<= 1e-4 and
-                              more than half the previous one), later fine
-                              and coarse sweeps run all-FP64.  Default 1.  */
+  int32_t promote_fp64;    /* RBC_MIXED only: 1 = before parareal_iterate's
+                              defect meets the FP32 rounding floor (near
+                              1e-7), switch to all-FP64 propagators: after
+                              iteration k >= 2, still above tol, if tol <
+                              1e-6 and the defect is <= 1e-3, or if the
+                              defect stalls (<= 1e-4 and more than half the
+                              previous one), the coarse sweeps from
+                              iteration k+1 and the fine runs from k+2 (the
+                              pipelined iteration starts those before the
+                              defect of k is known) run in FP64.  Default 1. */
+  int32_t pipelined;       /* parareal_iterate: 1 = overlap the serial coarse
+                              sweep with the fine runs (each slice's fine run
+                              starts as soon as its initial state is
+                              corrected; results identical to 0, the
+                              sweep-then-batch order).  Default 1.          */
 } rbc_params;
 
 /* Fill p with defaults (T_bot = 1, T_top = 0, ARS443, FP64, no sampling). */
@@ -149,7 +157,14 @@ rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first_slice,
  * Iteration 0 is the coarse prediction.  Iteration k runs F on slices
  * k-1..S-1 (the earlier ones are already exact), then the coarse
  * correction sweep; its defect (section 3.7) is the maximum over slices of
- * the relative L2 change of the state vector.  Stops when the defect is
+ * the relative L2 change of the state vector.
+ * With p.pipelined the fine run of slice n in iteration k+1 starts as soon
+ * as the sweep of iteration k has corrected U_n, on a stream of its own,
+ * batched with every other fine run in flight (runs of different slices and
+ * iterations advance in one launch); the sweep of iteration k+1 takes each
+ * F result as it completes.  The result is the same, bit for bit, as the
+ * sweep-then-batch order; the work after a converged iteration is started
+ * speculatively and discarded.  Stops when the defect is
  * <= tol, at k = k_max, or at k = n_slices (then U equals the serial fine
  * solution).  defect_hist_host[k-1] gets the defect of iteration k
  * (k_max entries).  nu_avg_hist_host, if not NULL and nu_stride > 0,
@@ -161,9 +176,26 @@ rbc_status parareal_iterate(rbc_handle h, double* U_dev, int32_t k_max, double t
                             int32_t* k_done_host, double* defect_hist_host,
                             double* nu_avg_hist_host);
 
-/* Iteration from which the last parareal_iterate ran its fine and coarse
- * sweeps in FP64 (promote_fp64), 0 if it never promoted. */
+/* First iteration whose fine runs the last parareal_iterate ran in FP64
+ * (promote_fp64; its coarse sweeps switched one iteration earlier), 0 if it
+ * never promoted. */
 rbc_status rbc_fine_fp64_from(rbc_handle h, int32_t* k_host);
+
+/* Scheduler statistics of the last pipelined parareal_iterate (tracing):
+ * host seconds spent admitting fine runs, enqueueing batched fine steps,
+ * enqueueing coarse work, reading reports and waiting for the device; the
+ * number of batched fine steps and of coarse chunks enqueued; the mean
+ * number of fine runs per batched step; the wall time of the call, and the
+ * wall time at which the report of iteration k was read (k = 0..15, the
+ * rest unset).  All zero before the first pipelined call. */
+typedef struct {
+  double wall_s;
+  double host_admit_s, host_fine_s, host_coarse_s, host_report_s, host_wait_s;
+  int64_t fine_steps, coarse_chunks;
+  double mean_runs_per_step;
+  double report_at_s[16];
+} rbc_pipeline_stats;
+rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out);
 
 /* Nusselt numbers of section 2.2 for n_states fine states (Eqs. 8-10):
  * nu_host[i] = (Nu_V, Nu_b, Nu_t).  Nu_b, Nu_t: -dT/dz of the horizontal

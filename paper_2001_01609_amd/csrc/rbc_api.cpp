@@ -1,7 +1,7 @@
 // C ABI of librbc (include/rbc.h): handle management, the seeded initial
-// state, the fine propagator over a batch of slices, the serial coarse sweep
-// and the Parareal iteration of Eq. 13 (section 3.1 of the paper), driven from
-// the host with every arithmetic step in the HIP kernels.
+// state, the fine propagator over a batch of slices and the diagnostics; the
+// coarse sweep and the Parareal iteration are in rbc_parareal.cpp.  Every
+// arithmetic step runs in the HIP kernels.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -9,34 +9,13 @@
 #include <string>
 #include <vector>
 
-#include "rbc_internal.hpp"
-
-struct rbc_ctx {
-  rbc_params p{};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  rbc::GridPlan fine, coarse;
-  rbc::GridPlan fine64, coarse64;   // all-FP64 plans for promoted sweeps (mixed + promote_fp64)
-  bool has64 = false;
-  int k_fp64 = 0;              // iteration the last parareal_iterate promoted at (0: never)
-  rbc::Work wf, wc, wf64, wc64;
-  int nf = 0, nc = 0;          // steps per slice
-  double* Xc = nullptr;        // coarse state being advanced
-  double* Fbuf = nullptr;      // [S][state]   F(U_n^(k-1))
-  double* Gbuf = nullptr;      // [S][cstate]  coarse part of G(U_n^k)
-  double* part = nullptr;      // [S+1][kCombineBlocks][2]
-  double* dscal = nullptr;     // [2] defect, non-finite flag
-  double* nu_f = nullptr;      // [S][nsf][3]
-  double* nu_c = nullptr;      // [S][nsc][3]
-  int nsf = 0, nsc = 0, stride_c = 0;
-  rbc::KernelTiming timing;    // fine-grid kernel timing (rbc_kernel_timing_*)
-  std::string err;
-};
+#include "rbc_ctx.hpp"
 
 namespace {
-
 thread_local std::string g_create_err;
+}  // namespace
 
+namespace rbc {
 rbc_status fail(rbc_handle h, rbc_status s, const std::string& msg) {
   if (h)
     h->err = msg;
@@ -44,13 +23,12 @@ rbc_status fail(rbc_handle h, rbc_status s, const std::string& msg) {
     g_create_err = msg;
   return s;
 }
+}  // namespace rbc
 
-#define HIPCHK(h, call)                                                                    \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return fail((h), RBC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
-  } while (0)
+namespace {
+
+using rbc::fail;
+#define HIPCHK RBC_HIPCHK
 
 int steps_for(double t0, double t1, int S, double dt, double* dt_used) {
   const double dT = (t1 - t0) / S;
@@ -120,9 +98,10 @@ size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::Gri
   size_t b = 0;
   b += size_t(4) * c.Mx * c.Nz * 8;                 // Xc
   b += S * 4 * f.Mx * f.Nz * 8;                     // F
+  b += (S + 2) * 4 * f.Mx * f.Nz * 8 + (S + 2) * 16; // state ring, slot records
   b += S * 4 * c.Mx * c.Nz * 8;                     // G
   b += (S + 1) * rbc::kCombineBlocks * 2 * 8 + 64;  // partials, scalars
-  b += S * size_t(nsf) * 3 * 8 + S * size_t(nsc) * 3 * 8;
+  b += 2 * S * size_t(nsf) * 3 * 8 + S * size_t(nsc) * 3 * 8;
   return b;
 }
 
@@ -130,13 +109,21 @@ void release(rbc_handle h) {
   if (!h) return;
   for (hipEvent_t e : h->timing.ev) (void)hipEventDestroy(e);
   h->timing.ev.clear();
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
+  h->evpool.clear();
+  if (h->cgraph) (void)hipGraphExecDestroy(h->cgraph);
+  if (h->cgraph64) (void)hipGraphExecDestroy(h->cgraph64);
+  if (h->fstream) (void)hipStreamDestroy(h->fstream);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
+  if (h->host_pin) (void)hipHostFree(h->host_pin);
   rbc::free_work(h->wf);
   rbc::free_work(h->wc);
   rbc::free_work(h->wf64);
   rbc::free_work(h->wc64);
   if (h->fine64.d_tables) (void)hipFree(h->fine64.d_tables);
   if (h->coarse64.d_tables) (void)hipFree(h->coarse64.d_tables);
-  for (void* q : {(void*)h->Xc, (void*)h->Fbuf, (void*)h->Gbuf, (void*)h->part, (void*)h->dscal,
+  for (void* q : {(void*)h->Xc, (void*)h->Fbuf, (void*)h->Xring, (void*)h->meta, (void*)h->Gbuf, (void*)h->part,
+                  (void*)h->dscal,
                   (void*)h->nu_f, (void*)h->nu_c, h->fine.d_tables, h->coarse.d_tables})
     if (q) (void)hipFree(q);
 }
@@ -170,6 +157,7 @@ rbc_status rbc_default_params(rbc_params* p) {
   p->nu_stride = 0; p->nu_t_start = 0;
   p->T_bot = 1; p->T_top = 0;
   p->promote_fp64 = 1;
+  p->pipelined = 1;
   return RBC_OK;
 }
 
@@ -194,12 +182,13 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes) {
   };
   int nsf, nsc, sc;
   sampling(p, nf, nc, dtf, dtc, &nsf, &nsc, &sc);
-  *device_bytes = tables(f) + tables(c) + rbc::work_bytes(f, p->n_slices) + rbc::work_bytes(c, 1) +
+  const int cap = p->n_slices + 2;
+  *device_bytes = tables(f) + tables(c) + rbc::work_bytes(f, cap) + rbc::work_bytes(c, 1) +
                   pararea_bytes(p, f, c, nsf, nsc);
   if (p->precision == RBC_MIXED && p->promote_fp64) {
     rbc::GridPlan f64 = f, c64 = c;
     f64.mixed = c64.mixed = false;
-    *device_bytes += tables(f64) + rbc::work_bytes(f64, p->n_slices) + tables(c64) + rbc::work_bytes(c64, 1);
+    *device_bytes += tables(f64) + rbc::work_bytes(f64, cap) + tables(c64) + rbc::work_bytes(c64, 1);
   }
   return RBC_OK;
 }
@@ -244,23 +233,33 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
       (h->has64 && ((he = rbc::upload_plan(h->fine64)) != hipSuccess ||
                     (he = rbc::upload_plan(h->coarse64)) != hipSuccess)))
     return bail(RBC_ERR_OOM, std::string("table upload: ") + hipGetErrorString(he));
-  if (h->has64 && ((he = rbc::alloc_work(h->fine64, p->n_slices, h->wf64)) != hipSuccess ||
+  h->ring_cap = p->n_slices + 2;
+  if (h->has64 && ((he = rbc::alloc_work(h->fine64, h->ring_cap, h->wf64)) != hipSuccess ||
                    (he = rbc::alloc_work(h->coarse64, 1, h->wc64)) != hipSuccess))
     return bail(RBC_ERR_OOM, std::string("workspace: ") + hipGetErrorString(he));
-  if ((he = rbc::alloc_work(h->fine, p->n_slices, h->wf)) != hipSuccess ||
+  if ((he = rbc::alloc_work(h->fine, h->ring_cap, h->wf)) != hipSuccess ||
       (he = rbc::alloc_work(h->coarse, 1, h->wc)) != hipSuccess)
     return bail(RBC_ERR_OOM, std::string("workspace: ") + hipGetErrorString(he));
   const size_t S = p->n_slices;
   const size_t fs = h->fine.dev.state, cs = h->coarse.dev.state;
   if (hipMalloc((void**)&h->Xc, cs * 8) != hipSuccess || hipMalloc((void**)&h->Fbuf, S * fs * 8) != hipSuccess ||
+      hipMalloc((void**)&h->Xring, size_t(h->ring_cap) * fs * 8) != hipSuccess ||
+      hipMalloc((void**)&h->meta, size_t(h->ring_cap) * sizeof(rbc::SlotMeta)) != hipSuccess ||
       hipMalloc((void**)&h->Gbuf, S * cs * 8) != hipSuccess ||
       hipMalloc((void**)&h->part, (S + 1) * rbc::kCombineBlocks * 2 * 8) != hipSuccess ||
       hipMalloc((void**)&h->dscal, 64) != hipSuccess)
     return bail(RBC_ERR_OOM, "parareal buffers");
-  if (h->nsf > 0 && hipMalloc((void**)&h->nu_f, S * h->nsf * 3 * 8) != hipSuccess)
+  if (h->nsf > 0 && hipMalloc((void**)&h->nu_f, 2 * S * h->nsf * 3 * 8) != hipSuccess)
     return bail(RBC_ERR_OOM, "nu sample buffer");
   if (h->nsc > 0 && hipMalloc((void**)&h->nu_c, S * h->nsc * 3 * 8) != hipSuccess)
     return bail(RBC_ERR_OOM, "nu sample buffer");
+  if (hipHostMalloc((void**)&h->host_pin, (2 + 2 * S * h->nsf * 3 + S * h->nsc * 3) * 8, hipHostMallocDefault) !=
+      hipSuccess)
+    return bail(RBC_ERR_OOM, "pinned host buffer");
+  // the pipelined iteration's two streams (default priority)
+  if ((he = hipStreamCreateWithFlags(&h->fstream, hipStreamNonBlocking)) != hipSuccess ||
+      (he = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking)) != hipSuccess)
+    return bail(RBC_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(he));
   *out = h;
   return RBC_OK;
 }
@@ -357,140 +356,6 @@ rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in, double* U_out, 
   const int ld = (nu_samples && stride > 0) ? n_steps / stride : 0;
   HIPCHK(h, rbc::launch_steps(h->fine, h->wf, U_out, n_slices, n_steps, ld > 0 ? nu_samples : nullptr, stride,
                               ld, h->stream, &h->timing));
-  return RBC_OK;
-}
-
-namespace {
-
-// Coarse sweep over slices [first, S): see rbc_coarse_sweep.  Coarse Nu
-// samples of slice n go to nu_c[n] when requested.
-rbc_status sweep(rbc_handle h, int mode, int first, double* U, const double* F, double* G, bool with_nu,
-                 bool use64 = false) {
-  const int S = h->p.n_slices;
-  const size_t fs = h->fine.dev.state, cs = h->coarse.dev.state;
-  rbc::GridPlan& cp = use64 ? h->coarse64 : h->coarse;
-  rbc::Work& cw = use64 ? h->wc64 : h->wc;
-  for (int n = first; n < S; ++n) {
-    HIPCHK(h, rbc::launch_restrict(h->fine, cp, U + n * fs, h->Xc, h->stream));
-    double* nu = (with_nu && h->nu_c) ? h->nu_c + size_t(n) * h->nsc * 3 : nullptr;
-    HIPCHK(h, rbc::launch_steps(cp, cw, h->Xc, 1, h->nc, nu, h->stride_c, h->nsc, h->stream));
-    HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, mode, U + (n + 1) * fs, mode == 1 ? F + n * fs : nullptr,
-                                  h->Xc, G + n * cs, h->part + size_t(n + 1) * rbc::kCombineBlocks * 2,
-                                  h->stream));
-  }
-  return RBC_OK;
-}
-
-rbc_status read_defect(rbc_handle h, int first, int last, double* defect, bool* bad) {
-  HIPCHK(h, rbc::launch_defect(h->part, first, last, h->dscal, h->stream));
-  double v[2];
-  HIPCHK(h, hipMemcpyAsync(v, h->dscal, 16, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  *defect = v[0];
-  *bad = v[1] != 0.0;
-  return RBC_OK;
-}
-
-// Time average of the Nu samples of slices [0, S) over [nu_t_start, t_end].
-rbc_status nu_average(rbc_handle h, const double* dev, int ns, int stride, double dt, double* out3) {
-  const int S = h->p.n_slices;
-  std::vector<double> buf(size_t(S) * ns * 3);
-  HIPCHK(h, hipMemcpyAsync(buf.data(), dev, buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  const double dT = (h->p.t_end - h->p.t0) / S;
-  double acc[3] = {0, 0, 0};
-  long cnt = 0;
-  for (int n = 0; n < S; ++n)
-    for (int q = 0; q < ns; ++q) {
-      const double t = h->p.t0 + n * dT + (q + 1) * stride * dt;
-      if (t < h->p.nu_t_start) continue;
-      for (int c = 0; c < 3; ++c) acc[c] += buf[(size_t(n) * ns + q) * 3 + c];
-      ++cnt;
-    }
-  for (int c = 0; c < 3; ++c) out3[c] = cnt ? acc[c] / cnt : NAN;
-  return RBC_OK;
-}
-
-}  // namespace
-
-rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first, double* U, const double* F, double* G,
-                            double* defect_host) {
-  if (!h || !U || !G) return fail(h, RBC_ERR_ARG, "null argument");
-  if (mode != 0 && mode != 1) return fail(h, RBC_ERR_ARG, "mode must be 0 (predict) or 1 (correct)");
-  if (mode == 1 && !F) return fail(h, RBC_ERR_ARG, "F is NULL in correct mode");
-  if (first < 0 || first > h->p.n_slices) return fail(h, RBC_ERR_ARG, "first_slice out of range");
-  rbc_status s = sweep(h, mode, first, U, F, G, false);
-  if (s != RBC_OK) return s;
-  if (defect_host) {
-    bool bad = false;
-    if ((s = read_defect(h, first + 1, h->p.n_slices + 1, defect_host, &bad)) != RBC_OK) return s;
-    if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in the coarse sweep");
-  }
-  return RBC_OK;
-}
-
-rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, int32_t* k_done,
-                            double* defect_hist, double* nu_hist) {
-  if (!h || !U || !k_done || !defect_hist) return fail(h, RBC_ERR_ARG, "null argument");
-  if (k_max < 0) return fail(h, RBC_ERR_ARG, "k_max < 0");
-  const int S = h->p.n_slices;
-  const size_t fs = h->fine.dev.state;
-  const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
-  rbc_status s;
-  *k_done = 0;
-  if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
-  if (want_nu) {
-    if (h->nsc > 0) {
-      if ((s = nu_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, nu_hist)) != RBC_OK) return s;
-    } else {
-      nu_hist[0] = nu_hist[1] = nu_hist[2] = NAN;
-    }
-  }
-  double defect = INFINITY, prev = INFINITY;
-  int k = 0;
-  bool f64 = false;
-  h->k_fp64 = 0;
-  while (k < k_max && k < S) {
-    ++k;
-    // F on slices k-1..S-1 from U^(k-1)
-    const int na = S - (k - 1);
-    double* nu = want_nu ? h->nu_f + size_t(k - 1) * h->nsf * 3 : nullptr;
-    HIPCHK(h, hipMemcpyAsync(h->Fbuf + (k - 1) * fs, U + (k - 1) * fs, size_t(na) * fs * 8,
-                             hipMemcpyDeviceToDevice, h->stream));
-    rbc::GridPlan& fp = f64 ? h->fine64 : h->fine;
-    rbc::Work& fw = f64 ? h->wf64 : h->wf;
-    HIPCHK(h, rbc::launch_steps(fp, fw, h->Fbuf + (k - 1) * fs, na, h->nf, nu, h->p.nu_stride, h->nsf,
-                                h->stream, &h->timing));
-    // U_k^k = F(U_(k-1)^(k-1)) exactly; then the correction sweep
-    HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, 2, U + k * fs, h->Fbuf + (k - 1) * fs, nullptr, nullptr,
-                                  h->part + size_t(k) * rbc::kCombineBlocks * 2, h->stream));
-    if ((s = sweep(h, 1, k, U, h->Fbuf, h->Gbuf, false, f64)) != RBC_OK) return s;
-    bool bad = false;
-    if ((s = read_defect(h, k, S + 1, &defect, &bad)) != RBC_OK) return s;
-    defect_hist[k - 1] = defect;
-    *k_done = k;
-    if (want_nu && (s = nu_average(h, h->nu_f, h->nsf, h->p.nu_stride, h->fine.dt, nu_hist + 3 * k)) != RBC_OK)
-      return s;
-    if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
-    if (defect <= tol) break;
-    // The FP32 rounding of the mixed propagators sets a defect floor near
-    // 1e-7: for a tolerance below 1e-6 switch to FP64 once the iteration
-    // error is small (1e-3) but still far above the switch's own jump, or
-    // whenever the defect stalls below 1e-4.
-    if (h->has64 && !f64 && k >= 2 &&
-        ((tol < 1e-6 && defect <= 1e-3) || (defect <= 1e-4 && defect > 0.5 * prev))) {
-      f64 = true;
-      h->k_fp64 = k + 1;
-    }
-    prev = defect;
-  }
-  if (k < S && !(defect <= tol) && tol > 0) return RBC_NOT_CONVERGED;
-  return RBC_OK;
-}
-
-rbc_status rbc_fine_fp64_from(rbc_handle h, int32_t* k) {
-  if (!h || !k) return fail(h, RBC_ERR_ARG, "null argument");
-  *k = h->k_fp64;
   return RBC_OK;
 }
 

@@ -117,6 +117,35 @@ struct KernelTiming {
 hipError_t launch_steps(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps,
                         double* nu_out, int nu_stride, int nu_ld, hipStream_t st,
                         KernelTiming* timing = nullptr);
+
+// Steps [step0, step1) of a run of n_total steps on `count` states held in
+// ring slots slot0, slot0 + 1, ... (mod w.cap) of X ([w.cap][state]).
+// step0 == 0 first transforms the initial states to the padded grid (so
+// step0 = step1 = 0 is that transform alone); the last stage of step
+// n_total - 1 skips the transform for a following step.  Nu samples as in
+// launch_steps, numbered from the start of the run.  Timed steps (see
+// KernelTiming) are chosen by timing_index + (step - step0).
+struct StepRange {
+  int slot0 = 0, count = 0;
+  int step0 = 0, step1 = 0, n_total = 0;
+  long timing_index = 0;
+};
+hipError_t launch_step_range(const GridPlan& g, Work& w, double* X, const StepRange& r, double* nu_out,
+                             int nu_stride, int nu_ld, hipStream_t st, KernelTiming* timing = nullptr);
+
+// Per-slot record of the pipelined Parareal's fine runs: the run's Nu
+// samples go to buffer `par` (iteration parity), slice n; it started at
+// virtual fine step `start`.
+struct SlotMeta {
+  int par, n, start, pad;
+};
+hipError_t launch_set_meta(SlotMeta* meta, int slot, SlotMeta v, hipStream_t st);
+// Nusselt numbers after virtual fine step t of the runs in ring slots
+// slot0.. (count of them, mod cap) of X: a run that has completed a
+// multiple q+1 of `stride` own steps writes nu[(par * S + n) * nsf + q][3].
+hipError_t launch_nusselt_ring(const GridPlan& g, const double* X, int slot0, int count, int cap,
+                               const SlotMeta* meta, int t, int stride, int nsf, int S, double* nu,
+                               hipStream_t st);
 // Explicit terms of one state (diagnostic): E = state-shaped FP64 array.
 hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st);
 // Nusselt numbers of n states: out[i*ld3 .. +3] (ld3 = stride in doubles).

@@ -39,6 +39,13 @@ __device__ __forceinline__ Cx<Real> cmul(Cx<Real> a, Cx<Real> b) {
 }
 template <typename Real>
 __device__ __forceinline__ Cx<Real> cadd(Cx<Real> a, Cx<Real> b) { return {a.x + b.x, a.y + b.y}; }
+
+// Batch position b -> slot of the state ring (slots slot0, slot0 + 1, ... mod
+// cap).  A plain batch is the ring read from slot 0 without wrapping.
+__device__ __forceinline__ int ring_slot(int b, int slot0, int cap) {
+  const int s = slot0 + b;
+  return s >= cap ? s - cap : s;
+}
 template <typename Real>
 __device__ __forceinline__ Cx<Real> csub(Cx<Real> a, Cx<Real> b) { return {a.x - b.x, a.y - b.y}; }
 
@@ -182,11 +189,13 @@ __device__ __forceinline__ Real wave_sum(Real v) {
 // u w.
 template <typename Real, int PX, int RB>
 __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* __restrict__ Q,
-                                                        Real* __restrict__ Nh, Real* __restrict__ qbar) {
+                                                        Real* __restrict__ Nh, Real* __restrict__ qbar,
+                                                        int slot0, int cap) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = g.Pz, Mx = g.Mx, MT = g.MT, ntile = g.ntile;
   const int ngrp = Pz / RB;
-  const int s = blockIdx.x / ngrp, jg = blockIdx.x - s * ngrp;
+  const int b = blockIdx.x / ngrp, jg = blockIdx.x - b * ngrp;
+  const int s = ring_slot(b, slot0, cap);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = jg * RB + wv;
   Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem) + wv * 3 * PX;   // this row's [3][PX]
@@ -246,6 +255,7 @@ struct StageArgs {
   int stage;           // i = 1..s
   int s;               // implicit stages
   int cap;             // slices the history arrays are sized for
+  int slot0;           // ring slot of the first state of the batch
   int store_E, store_LY, write_X, do_zinv;
   double hae[kMaxStages];   // h a_ij (explicit), j < i
   double hai[kMaxStages];   // h a~_ij (implicit), 1 <= j <= i
@@ -544,7 +554,8 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   extern __shared__ __align__(16) unsigned char smem[];
   const int Mx = g.Mx;
   const int ntile = g.ntile;   // ceil(Mx / MT)
-  const int s = blockIdx.x / ntile, tile = blockIdx.x - s * ntile;
+  const int b = blockIdx.x / ntile, tile = blockIdx.x - b * ntile;
+  const int s = ring_slot(b, a.slot0, a.cap);
   const int m0 = tile * MT;
   const int st = g.state;
   double* sY = reinterpret_cast<double*>(smem);
@@ -1050,11 +1061,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
 // One block per state.  <w T> = sum_{m>=1} Re(w_m^T J conj(T_m)) with
 // J_ab = int_{-1}^{1} T_a T_b = (I(a+b) + I(|a-b|))/2, I(n) = 2/(1-n^2) for
 // even n; w_m = -i k psi_m.  Fixed-order partial sums and tree reduction.
-__global__ void __launch_bounds__(kBlock)
-nusselt_kernel(GridDev g, const double* __restrict__ X, double* __restrict__ out, int ld3) {
-  __shared__ double red[kBlock];
+__device__ void nusselt_block(const GridDev& g, const double* __restrict__ x, double* __restrict__ o,
+                              double* red) {
   const int Nz = g.Nz, Mx = g.Mx;
-  const double* x = X + size_t(blockIdx.x) * g.state;
   double acc = 0;
   for (int e = threadIdx.x; e < (Mx - 1) * Nz; e += blockDim.x) {
     const int m = 1 + e / Nz, aa = e % Nz;
@@ -1088,11 +1097,33 @@ nusselt_kernel(GridDev g, const double* __restrict__ X, double* __restrict__ out
       t0 += tm[n] * sgn;
       t1 += tm[n];
     }
-    double* o = out + size_t(blockIdx.x) * ld3;
     o[0] = (t0 - t1) / g.Lz + g.sqrtRaPr * red[0];
     o[1] = -g.scale * nb;
     o[2] = -g.scale * nt;
   }
+}
+
+__global__ void __launch_bounds__(kBlock)
+nusselt_kernel(GridDev g, const double* __restrict__ X, double* __restrict__ out, int ld3) {
+  __shared__ double red[kBlock];
+  nusselt_block(g, X + size_t(blockIdx.x) * g.state, out + size_t(blockIdx.x) * ld3, red);
+}
+
+// Ring form for the pipelined fine runs (block-uniform early exit).
+__global__ void __launch_bounds__(kBlock)
+nusselt_ring_kernel(GridDev g, const double* __restrict__ X, int slot0, int cap, const SlotMeta* __restrict__ meta,
+                    int t, int stride, int nsf, int S, double* __restrict__ nu) {
+  __shared__ double red[kBlock];
+  const int slot = ring_slot(blockIdx.x, slot0, cap);
+  const SlotMeta m = meta[slot];
+  const int d = t - m.start;
+  if (d <= 0 || d % stride != 0 || d / stride > nsf) return;
+  const int q = d / stride - 1;
+  nusselt_block(g, X + size_t(slot) * g.state, nu + ((size_t(m.par) * S + m.n) * nsf + q) * 3, red);
+}
+
+__global__ void set_meta_kernel(SlotMeta* meta, int slot, SlotMeta v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) meta[slot] = v;
 }
 
 // ----------------------------------------------------- transfer / correction ---
@@ -1230,7 +1261,7 @@ constexpr int xpass_rows() {
 }
 
 template <typename Real, int PX>
-hipError_t run_xpass_t(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
+hipError_t run_xpass_t(const GridPlan& g, Work& w, int slot0, int n_slices, hipStream_t st) {
   const GridDev& d = g.dev;
   constexpr int RB = xpass_rows<Real, PX>();
   // a small batch (the single-slice coarse sweep) would leave most CUs idle
@@ -1238,28 +1269,28 @@ hipError_t run_xpass_t(const GridPlan& g, Work& w, int n_slices, hipStream_t st)
   if (RB > 1 && n_slices * (d.Pz / RB) < 256) {
     const size_t lds = sizeof(Real) * 2 * 3 * size_t(PX);
     hipLaunchKernelGGL((xpass_kernel<Real, PX, 1>), dim3(n_slices * d.Pz), dim3(64), lds, st, d, (const Real*)w.Q,
-                       (Real*)w.Nh, (Real*)w.qbar);
+                       (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
   } else {
     const size_t lds = sizeof(Real) * 2 * 3 * size_t(PX) * RB;
     hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(n_slices * (d.Pz / RB)), dim3(64 * RB), lds, st, d,
-                       (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar);
+                       (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
   }
   return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t run_xpass(const GridPlan& g, Work& w, int n_slices, hipStream_t st) {
+hipError_t run_xpass(const GridPlan& g, Work& w, int slot0, int n_slices, hipStream_t st) {
   switch (g.dev.Px) {
-    case 6: return run_xpass_t<Real, 6>(g, w, n_slices, st);
-    case 12: return run_xpass_t<Real, 12>(g, w, n_slices, st);
-    case 24: return run_xpass_t<Real, 24>(g, w, n_slices, st);
-    case 48: return run_xpass_t<Real, 48>(g, w, n_slices, st);
-    case 96: return run_xpass_t<Real, 96>(g, w, n_slices, st);
-    case 192: return run_xpass_t<Real, 192>(g, w, n_slices, st);
-    case 384: return run_xpass_t<Real, 384>(g, w, n_slices, st);
-    case 768: return run_xpass_t<Real, 768>(g, w, n_slices, st);
-    case 1536: return run_xpass_t<Real, 1536>(g, w, n_slices, st);
-    case 3072: return run_xpass_t<Real, 3072>(g, w, n_slices, st);
+    case 6: return run_xpass_t<Real, 6>(g, w, slot0, n_slices, st);
+    case 12: return run_xpass_t<Real, 12>(g, w, slot0, n_slices, st);
+    case 24: return run_xpass_t<Real, 24>(g, w, slot0, n_slices, st);
+    case 48: return run_xpass_t<Real, 48>(g, w, slot0, n_slices, st);
+    case 96: return run_xpass_t<Real, 96>(g, w, slot0, n_slices, st);
+    case 192: return run_xpass_t<Real, 192>(g, w, slot0, n_slices, st);
+    case 384: return run_xpass_t<Real, 384>(g, w, slot0, n_slices, st);
+    case 768: return run_xpass_t<Real, 768>(g, w, slot0, n_slices, st);
+    case 1536: return run_xpass_t<Real, 1536>(g, w, slot0, n_slices, st);
+    case 3072: return run_xpass_t<Real, 3072>(g, w, slot0, n_slices, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1276,31 +1307,34 @@ hipError_t timing_mark(KernelTiming* t, hipStream_t st) {
 }
 
 template <typename Real>
-hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps, double* nu_out,
-                      int nu_stride, int nu_ld, hipStream_t st, KernelTiming* tm) {
-  if (n_steps <= 0) return hipSuccess;
+hipError_t steps_impl(const GridPlan& g, Work& w, double* X, const StepRange& r, double* nu_out, int nu_stride,
+                      int nu_ld, hipStream_t st, KernelTiming* tm) {
   const Tableau& tb = g.tab;
-  StageArgs a{};
-  a.mode = kModeZinv;
-  a.do_zinv = 1;
-  a.cap = w.cap;
-  a.s = tb.s;
-  hipError_t e = run_stage<Real>(g, w, a, X, n_slices, nullptr, st);
-  if (e != hipSuccess) return e;
-  int sample = 0;
-  for (int step = 0; step < n_steps; ++step) {
-    const bool last = (step == n_steps - 1);
-    const bool timed = tm && tm->every > 0 && step % tm->every == 0 &&
+  hipError_t e;
+  if (r.step0 == 0) {
+    StageArgs a{};
+    a.mode = kModeZinv;
+    a.do_zinv = 1;
+    a.cap = w.cap;
+    a.slot0 = r.slot0;
+    a.s = tb.s;
+    if ((e = run_stage<Real>(g, w, a, X, r.count, nullptr, st)) != hipSuccess) return e;
+  }
+  for (int step = r.step0; step < r.step1; ++step) {
+    const bool last = (step == r.n_total - 1);
+    const long ti = r.timing_index + (step - r.step0);
+    const bool timed = tm && tm->every > 0 && ti % tm->every == 0 &&
                        tm->used + 2 * tb.s <= 2 * KernelTiming::kMaxPairs;
     for (int i = 1; i <= tb.s; ++i) {
       if (timed && tm->kernel == 1 && (e = timing_mark(tm, st)) != hipSuccess) return e;
-      if ((e = run_xpass<Real>(g, w, n_slices, st)) != hipSuccess) return e;
+      if ((e = run_xpass<Real>(g, w, r.slot0, r.count, st)) != hipSuccess) return e;
       if (timed && tm->kernel == 1 && (e = timing_mark(tm, st)) != hipSuccess) return e;
       StageArgs b{};
       b.mode = kModeStage;
       b.stage = i;
       b.s = tb.s;
       b.cap = w.cap;
+      b.slot0 = r.slot0;
       b.store_E = (i < tb.s);
       b.store_LY = (i < tb.s);
       b.write_X = (i == tb.s);
@@ -1309,14 +1343,16 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n
       for (int j = 1; j <= i; ++j) b.hai[j] = g.dt * tb.ai[i][j];
       b.haii = g.dt * tb.ai[i][i];
       if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
-      if ((e = run_stage<Real>(g, w, b, X, n_slices, nullptr, st)) != hipSuccess) return e;
+      if ((e = run_stage<Real>(g, w, b, X, r.count, nullptr, st)) != hipSuccess) return e;
       if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
     }
     if (nu_out && nu_stride > 0 && (step + 1) % nu_stride == 0) {
-      hipLaunchKernelGGL(nusselt_kernel, dim3(n_slices), dim3(kBlock), 0, st, g.dev, X,
-                         nu_out + size_t(sample) * 3, nu_ld * 3);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      ++sample;
+      const int sample = (step + 1) / nu_stride - 1;
+      if (sample < nu_ld) {
+        hipLaunchKernelGGL(nusselt_kernel, dim3(r.count), dim3(kBlock), 0, st, g.dev, X, nu_out + size_t(sample) * 3,
+                           nu_ld * 3);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
     }
   }
   return hipSuccess;
@@ -1324,10 +1360,25 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, int n_slices, int n
 
 }  // namespace
 
+hipError_t launch_step_range(const GridPlan& g, Work& w, double* X, const StepRange& r, double* nu_out,
+                             int nu_stride, int nu_ld, hipStream_t st, KernelTiming* tm) {
+  if (r.count < 1 || r.count > w.cap || r.slot0 < 0 || r.slot0 >= w.cap) return hipErrorInvalidValue;
+  // the Nu launch indexes X by batch position: plain batches only
+  if (nu_out && nu_stride > 0 && r.slot0 != 0) return hipErrorInvalidValue;
+  if (g.mixed) return steps_impl<float>(g, w, X, r, nu_out, nu_stride, nu_ld, st, tm);
+  return steps_impl<double>(g, w, X, r, nu_out, nu_stride, nu_ld, st, tm);
+}
+
 hipError_t launch_steps(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps, double* nu_out,
                         int nu_stride, int nu_ld, hipStream_t st, KernelTiming* tm) {
-  if (g.mixed) return steps_impl<float>(g, w, X, n_slices, n_steps, nu_out, nu_stride, nu_ld, st, tm);
-  return steps_impl<double>(g, w, X, n_slices, n_steps, nu_out, nu_stride, nu_ld, st, tm);
+  if (n_steps <= 0) return hipSuccess;
+  StepRange r;
+  r.slot0 = 0;
+  r.count = n_slices;
+  r.step0 = 0;
+  r.step1 = n_steps;
+  r.n_total = n_steps;
+  return launch_step_range(g, w, X, r, nu_out, nu_stride, nu_ld, st, tm);
 }
 
 hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st) {
@@ -1340,14 +1391,27 @@ hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* 
   double* Xm = const_cast<double*>(X);
   if (g.mixed) {
     if ((e = run_stage<float>(g, w, a, Xm, 1, nullptr, st)) != hipSuccess) return e;
-    if ((e = run_xpass<float>(g, w, 1, st)) != hipSuccess) return e;
+    if ((e = run_xpass<float>(g, w, 0, 1, st)) != hipSuccess) return e;
     a.mode = kModeExplicit;
     return run_stage<float>(g, w, a, Xm, 1, E, st);
   }
   if ((e = run_stage<double>(g, w, a, Xm, 1, nullptr, st)) != hipSuccess) return e;
-  if ((e = run_xpass<double>(g, w, 1, st)) != hipSuccess) return e;
+  if ((e = run_xpass<double>(g, w, 0, 1, st)) != hipSuccess) return e;
   a.mode = kModeExplicit;
   return run_stage<double>(g, w, a, Xm, 1, E, st);
+}
+
+hipError_t launch_set_meta(SlotMeta* meta, int slot, SlotMeta v, hipStream_t st) {
+  hipLaunchKernelGGL(set_meta_kernel, dim3(1), dim3(64), 0, st, meta, slot, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_nusselt_ring(const GridPlan& g, const double* X, int slot0, int count, int cap,
+                               const SlotMeta* meta, int t, int stride, int nsf, int S, double* nu, hipStream_t st) {
+  if (count < 1 || count > cap || slot0 < 0 || slot0 >= cap || stride < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nusselt_ring_kernel, dim3(count), dim3(kBlock), 0, st, g.dev, X, slot0, cap, meta, t, stride,
+                     nsf, S, nu);
+  return hipGetLastError();
 }
 
 hipError_t launch_nusselt(const GridPlan& g, const double* X, int n, double* out, int ld3, hipStream_t st) {

@@ -1,0 +1,726 @@
+// Parareal (section 3.1, Eq. 13) around the batched fine propagator: the
+// serial coarse sweep, the sweep-then-batch iteration, and the pipelined
+// iteration, a host scheduler that overlaps the two propagators on two
+// streams.
+//
+// Pipelined iteration.  The fine run F(U_n^(k-1)) of iteration k needs only
+// U_n^(k-1), which the coarse sweep of iteration k-1 corrects slice by
+// slice, and the sweep of iteration k needs F(U_n^(k-1)) only when it reaches
+// slice n.  So each fine run (a "job") is admitted as soon as its initial
+// state exists, into a ring of state slots; every fine launch advances all
+// jobs in flight by one step, whatever their slice and iteration (the
+// kernels are batch-invariant, so a job's result does not depend on its
+// batch); a job leaves after its n_f steps, and the coarse stream, which
+// waits for it with an event, corrects the next slice.  Jobs enter and leave
+// in one order, so those in flight always fill a contiguous range of the
+// ring and one launch covers them.  The host never blocks the fine stream on
+// the coarse one: it admits a job only after polling that the producing
+// coarse task has completed.  Stream-order constraints:
+//   - job (k, n) reads U_n^(k-1) (copied into its slot at admission): after
+//     the coarse task that wrote it (polled);
+//   - the coarse task that overwrites U_n^(k-1) with U_n^k waits for that
+//     copy (event);
+//   - a slot is reused only after the coarse task that read the previous
+//     job's result has completed (polled);
+//   - the sweep of iteration k starts after the host has read the defect of
+//     iteration k-1 (stop test, precision switch).
+// The jobs of iteration k+1 start before the defect of iteration k is known:
+// after convergence they are abandoned.
+// Two host threads enqueue the work, one per stream (a kernel launch costs
+// the host microseconds, and one thread could not keep both streams fed):
+// the fine thread admits jobs and enqueues batched steps, the calling thread
+// enqueues coarse work and reads the reports.  They share the admission and
+// completion counters and the coarse task counter (atomics, release on
+// write after the matching event is recorded, acquire on read).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "rbc_ctx.hpp"
+
+using rbc::fail;
+
+namespace {
+
+// Coarse sweep over slices [first, S): see rbc_coarse_sweep.  Coarse Nu
+// samples of slice n go to nu_c[n] when requested.
+rbc_status sweep(rbc_handle h, int mode, int first, double* U, const double* F, double* G, bool with_nu,
+                 bool use64 = false) {
+  const int S = h->p.n_slices;
+  const size_t fs = h->fine.dev.state, cs = h->coarse.dev.state;
+  rbc::GridPlan& cp = use64 ? h->coarse64 : h->coarse;
+  rbc::Work& cw = use64 ? h->wc64 : h->wc;
+  for (int n = first; n < S; ++n) {
+    RBC_HIPCHK(h, rbc::launch_restrict(h->fine, cp, U + n * fs, h->Xc, h->stream));
+    double* nu = (with_nu && h->nu_c) ? h->nu_c + size_t(n) * h->nsc * 3 : nullptr;
+    RBC_HIPCHK(h, rbc::launch_steps(cp, cw, h->Xc, 1, h->nc, nu, h->stride_c, h->nsc, h->stream));
+    RBC_HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, mode, U + (n + 1) * fs, mode == 1 ? F + n * fs : nullptr,
+                                      h->Xc, G + n * cs, h->part + size_t(n + 1) * rbc::kCombineBlocks * 2,
+                                      h->stream));
+  }
+  return RBC_OK;
+}
+
+rbc_status read_defect(rbc_handle h, int first, int last, double* defect, bool* bad) {
+  RBC_HIPCHK(h, rbc::launch_defect(h->part, first, last, h->dscal, h->stream));
+  double v[2];
+  RBC_HIPCHK(h, hipMemcpyAsync(v, h->dscal, 16, hipMemcpyDeviceToHost, h->stream));
+  RBC_HIPCHK(h, hipStreamSynchronize(h->stream));
+  *defect = v[0];
+  *bad = v[1] != 0.0;
+  return RBC_OK;
+}
+
+// Time average over [nu_t_start, t_end] of the Nu samples of slices [0, S);
+// slice(n) points at slice n's [ns][3] samples.  Fixed summation order.
+template <typename SliceFn>
+void nu_average_host(rbc_handle h, int ns, int stride, double dt, SliceFn slice, double* out3) {
+  const int S = h->p.n_slices;
+  const double dT = (h->p.t_end - h->p.t0) / S;
+  double acc[3] = {0, 0, 0};
+  long cnt = 0;
+  for (int n = 0; n < S; ++n) {
+    const double* b = slice(n);
+    for (int q = 0; q < ns; ++q) {
+      const double t = h->p.t0 + n * dT + (q + 1) * stride * dt;
+      if (t < h->p.nu_t_start) continue;
+      for (int c = 0; c < 3; ++c) acc[c] += b[size_t(q) * 3 + c];
+      ++cnt;
+    }
+  }
+  for (int c = 0; c < 3; ++c) out3[c] = cnt ? acc[c] / cnt : NAN;
+}
+
+rbc_status nu_average(rbc_handle h, const double* dev, int ns, int stride, double dt, double* out3) {
+  const int S = h->p.n_slices;
+  std::vector<double> buf(size_t(S) * ns * 3);
+  RBC_HIPCHK(h, hipMemcpyAsync(buf.data(), dev, buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  RBC_HIPCHK(h, hipStreamSynchronize(h->stream));
+  nu_average_host(h, ns, stride, dt, [&](int n) { return buf.data() + size_t(n) * ns * 3; }, out3);
+  return RBC_OK;
+}
+
+// The precision switch of promote_fp64, decided after iteration k (defect
+// d, previous defect prev): the coarse sweeps switch from k + 1, the fine
+// runs from k + 2.
+bool promote_now(rbc_handle h, int k, double d, double prev, double tol) {
+  return h->has64 && k >= 2 && ((tol < 1e-6 && d <= 1e-3) || (d <= 1e-4 && d > 0.5 * prev));
+}
+
+// ---------------------------------------------------------------- sweep-then-batch ---
+
+rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, int* k_done, double* defect_hist,
+                               double* nu_hist) {
+  const int S = h->p.n_slices;
+  const size_t fs = h->fine.dev.state;
+  const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
+  rbc_status s;
+  *k_done = 0;
+  if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
+  if (want_nu) {
+    if (h->nsc > 0) {
+      if ((s = nu_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, nu_hist)) != RBC_OK) return s;
+    } else {
+      nu_hist[0] = nu_hist[1] = nu_hist[2] = NAN;
+    }
+  }
+  double defect = INFINITY, prev = INFINITY;
+  int k = 0, kG64 = INT_MAX, kF64 = INT_MAX;
+  while (k < k_max && k < S) {
+    ++k;
+    // F on slices k-1..S-1 from U^(k-1)
+    const int na = S - (k - 1);
+    double* nu = want_nu ? h->nu_f + size_t(k - 1) * h->nsf * 3 : nullptr;
+    RBC_HIPCHK(h, hipMemcpyAsync(h->Fbuf + (k - 1) * fs, U + (k - 1) * fs, size_t(na) * fs * 8,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    const bool f64 = k >= kF64;
+    rbc::GridPlan& fp = f64 ? h->fine64 : h->fine;
+    rbc::Work& fw = f64 ? h->wf64 : h->wf;
+    RBC_HIPCHK(h, rbc::launch_steps(fp, fw, h->Fbuf + (k - 1) * fs, na, h->nf, nu, h->p.nu_stride, h->nsf,
+                                    h->stream, f64 ? nullptr : &h->timing));
+    // U_k^k = F(U_(k-1)^(k-1)) exactly; then the correction sweep
+    RBC_HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, 2, U + k * fs, h->Fbuf + (k - 1) * fs, nullptr, nullptr,
+                                      h->part + size_t(k) * rbc::kCombineBlocks * 2, h->stream));
+    if ((s = sweep(h, 1, k, U, h->Fbuf, h->Gbuf, false, k >= kG64)) != RBC_OK) return s;
+    bool bad = false;
+    if ((s = read_defect(h, k, S + 1, &defect, &bad)) != RBC_OK) return s;
+    defect_hist[k - 1] = defect;
+    *k_done = k;
+    if (want_nu && (s = nu_average(h, h->nu_f, h->nsf, h->p.nu_stride, h->fine.dt, nu_hist + 3 * k)) != RBC_OK)
+      return s;
+    if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
+    if (defect <= tol) break;
+    if (kG64 == INT_MAX && promote_now(h, k, defect, prev, tol)) {
+      kG64 = k + 1;
+      kF64 = k + 2;
+    }
+    prev = defect;
+  }
+  h->k_fp64 = (kF64 <= k) ? kF64 : 0;
+  if (k < S && !(defect <= tol) && tol > 0) return RBC_NOT_CONVERGED;
+  return RBC_OK;
+}
+
+// ---------------------------------------------------------------- pipelined ---
+
+constexpr int kFDepth = 6;    // batched fine steps in flight on the fine stream
+constexpr int kGDepth = 16;   // coarse chunks (kCoarseGraphSteps steps each) in flight on the coarse stream
+
+enum TaskKind { kPredict, kCopy, kCorrect, kReport };
+struct Task {
+  TaskKind kind;
+  int k, n;
+};
+struct Job {
+  int k, n, slot, start;   // iteration, slice (input U_n^(k-1)), ring slot, first virtual step
+  bool f64;
+};
+
+class Pipeline {
+ public:
+  Pipeline(rbc_handle h, double* U, int K, double tol, bool want_nu, int* k_done, double* defect_hist,
+           double* nu_hist)
+      : h_(h), U_(U), S_(h->p.n_slices), K_(K), nf_(h->nf), nc_(h->nc), cap_(h->ring_cap),
+        stride_(h->p.nu_stride), tol_(tol), want_nu_(want_nu), k_done_(k_done), defect_hist_(defect_hist),
+        nu_hist_(nu_hist), fs_(h->fine.dev.state), cs_(h->coarse.dev.state), F_(h->fstream), G_(h->gstream) {}
+
+  rbc_status run();
+
+ private:
+  rbc_handle h_;
+  double* U_;
+  const int S_, K_, nf_, nc_, cap_, stride_;
+  const double tol_;
+  const bool want_nu_;
+  int* k_done_;
+  double* defect_hist_;
+  double* nu_hist_;
+  const size_t fs_, cs_;
+  hipStream_t F_, G_;
+
+  std::vector<Job> jobs_;
+  std::vector<int> job_base_;    // [K+1]: index of job (k, k-1)
+  std::vector<Task> tasks_;
+  std::vector<int> task_base_;   // [K+1]: index of Copy(k), k >= 1
+  hipEvent_t *ev_admit_ = nullptr, *ev_done_ = nullptr, *ev_task_ = nullptr;
+  hipEvent_t *ev_step_ = nullptr, *ev_chunk_ = nullptr, ev_entry_ = nullptr;
+
+  // fine thread: writes jn_, ja_ (shared), owns t_, freal_
+  std::atomic<int> jn_{0}, ja_{0};   // next job to admit, first unfinished job
+  int t_ = 0;                        // virtual fine step
+  long freal_ = 0;                   // batched fine steps enqueued
+  // coarse thread: writes gi_, kF64_ (shared), owns the rest
+  std::atomic<int> gi_{0};           // next coarse task
+  int gstep_ = -1;                   // coarse steps enqueued of task gi_ (-1: not started)
+  long gchunks_ = 0;
+  int kG64_ = INT_MAX;
+  std::atomic<int> kF64_{INT_MAX};
+  int processed_ = -1, pending_ = -1;   // last report read, report in flight
+  double defect_ = INFINITY, prev_ = INFINITY;
+  // both
+  std::atomic<bool> stop_{false};
+  std::atomic<long> progress_{0};
+  std::mutex err_mu_;
+  rbc_status status_ = RBC_OK;       // first error (under err_mu_)
+  // statistics (per thread, merged at the end)
+  double f_admit_s_ = 0, f_fine_s_ = 0, f_wait_s_ = 0, runs_ = 0;
+  long f_steps_ = 0;
+
+  int job_index(int k, int n) const { return job_base_[k] + (n - (k - 1)); }
+  int producer(const Job& J) const {
+    if (J.n == 0) return -1;                                          // U_0
+    if (J.k == 1) return J.n - 1;                                     // Predict(0, n-1)
+    if (J.n == J.k - 1) return task_base_[J.k - 1];                   // Copy(k-1)
+    return task_base_[J.k - 1] + 1 + (J.n - 1 - (J.k - 1));           // Correct(k-1, n-1)
+  }
+  int consumer(const Job& J) const {
+    if (J.n == J.k - 1) return task_base_[J.k];                       // Copy(k)
+    return task_base_[J.k] + 1 + (J.n - J.k);                         // Correct(k, n)
+  }
+  int report_task(int k) const { return k == 0 ? S_ : task_base_[k] + 1 + (S_ - k); }
+
+  // 1 complete, 0 pending, -1 error (status_ set)
+  int query(hipEvent_t e) {
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipSuccess) return 1;
+    if (r == hipErrorNotReady) return 0;
+    herr(r, "hipEventQuery");
+    return -1;
+  }
+  int task_done(int ti) { return ti < gi_.load(std::memory_order_acquire) ? query(ev_task_[ti]) : 0; }
+  void seterr(rbc_status st, const std::string& msg) {
+    std::lock_guard<std::mutex> lk(err_mu_);
+    if (status_ == RBC_OK) status_ = fail(h_, st, msg);
+    stop_.store(true);
+  }
+  rbc_status status() {
+    std::lock_guard<std::mutex> lk(err_mu_);
+    return status_;
+  }
+  void herr(hipError_t e, const char* what) { seterr(RBC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)); }
+  bool ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    herr(e, what);
+    return false;
+  }
+
+  rbc_status setup();
+  rbc_status build_graph(rbc::GridPlan& cp, rbc::Work& cw, hipGraphExec_t* ex);
+  int admit();
+  int fine_step();
+  int coarse_work();
+  int poll_report();
+  void fine_loop();
+};
+
+// Captures kCoarseGraphSteps coarse steps on Xc (the steps inside a coarse
+// run: no first transform, no Nu samples, never the last step) as a graph;
+// every coarse run replays it.  Kernel arguments are fixed per plan.
+rbc_status Pipeline::build_graph(rbc::GridPlan& cp, rbc::Work& cw, hipGraphExec_t* ex) {
+  if (*ex) return RBC_OK;
+  hipStream_t cs = nullptr;
+  RBC_HIPCHK(h_, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rbc::StepRange r;
+    r.slot0 = 0;
+    r.count = 1;
+    r.step0 = 1;
+    r.step1 = 1 + rbc::kCoarseGraphSteps;
+    r.n_total = INT_MAX;
+    const hipError_t e1 = rbc::launch_step_range(cp, cw, h_->Xc, r, nullptr, 0, 0, cs, nullptr);
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    e = (e1 != hipSuccess) ? e1 : e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    *ex = nullptr;
+    return fail(h_, RBC_ERR_HIP, std::string("coarse step graph: ") + hipGetErrorString(e));
+  }
+  return RBC_OK;
+}
+
+rbc_status Pipeline::setup() {
+  rbc_status s_;
+  for (int k = 0; k <= K_; ++k) job_base_.push_back(0);
+  for (int k = 1; k <= K_; ++k) {
+    job_base_[k] = int(jobs_.size());
+    for (int n = k - 1; n < S_; ++n) jobs_.push_back({k, n, int(jobs_.size() % cap_), -1, false});
+  }
+  task_base_.assign(K_ + 1, 0);
+  for (int n = 0; n < S_; ++n) tasks_.push_back({kPredict, 0, n});
+  tasks_.push_back({kReport, 0, -1});
+  for (int k = 1; k <= K_; ++k) {
+    task_base_[k] = int(tasks_.size());
+    tasks_.push_back({kCopy, k, k - 1});
+    for (int n = k; n < S_; ++n) tasks_.push_back({kCorrect, k, n});
+    tasks_.push_back({kReport, k, -1});
+  }
+  const size_t need = 2 * jobs_.size() + tasks_.size() + kFDepth + kGDepth + 1;
+  while (h_->evpool.size() < need) {
+    hipEvent_t e;
+    RBC_HIPCHK(h_, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h_->evpool.push_back(e);
+  }
+  if ((s_ = build_graph(h_->coarse, h_->wc, &h_->cgraph)) != RBC_OK) return s_;
+  if (h_->has64 && (s_ = build_graph(h_->coarse64, h_->wc64, &h_->cgraph64)) != RBC_OK) return s_;
+  hipEvent_t* p = h_->evpool.data();
+  ev_admit_ = p; p += jobs_.size();
+  ev_done_ = p; p += jobs_.size();
+  ev_task_ = p; p += tasks_.size();
+  ev_step_ = p; p += kFDepth;
+  ev_chunk_ = p; p += kGDepth;
+  ev_entry_ = *p;
+  return RBC_OK;
+}
+
+// Admits jobs in order while their input exists and a slot is free.
+int Pipeline::admit() {
+  int did = 0;
+  while (jn_ < int(jobs_.size())) {
+    Job& J = jobs_[jn_];
+    const int p = producer(J);
+    if (p >= 0) {
+      const int q = task_done(p);
+      if (q <= 0) return q < 0 ? -1 : did;
+    }
+    if (jn_ >= cap_) {
+      const int q = task_done(consumer(jobs_[jn_ - cap_]));
+      if (q <= 0) return q < 0 ? -1 : did;
+    }
+    if (want_nu_) {   // runs start on multiples of the sampling stride
+      if (ja_ < jn_) {
+        if (t_ % stride_ != 0) return did;
+      } else {
+        t_ = (t_ + stride_ - 1) / stride_ * stride_;
+      }
+    }
+    J.f64 = J.k >= kF64_;   // final: the report of iteration k-2 has been read
+    J.start = t_;
+    rbc::GridPlan& fp = J.f64 ? h_->fine64 : h_->fine;
+    rbc::Work& fw = J.f64 ? h_->wf64 : h_->wf;
+    if (want_nu_ && !ok(rbc::launch_set_meta(h_->meta, J.slot, {J.k & 1, J.n, J.start, 0}, F_), "set_meta"))
+      return -1;
+    if (!ok(hipMemcpyAsync(h_->Xring + J.slot * fs_, U_ + J.n * fs_, fs_ * 8, hipMemcpyDeviceToDevice, F_),
+            "hipMemcpyAsync"))
+      return -1;
+    rbc::StepRange r;
+    r.slot0 = J.slot;
+    r.count = 1;
+    r.step0 = r.step1 = 0;   // the inverse transform of the initial state only
+    r.n_total = 1;
+    if (!ok(rbc::launch_step_range(fp, fw, h_->Xring, r, nullptr, 0, 0, F_), "zinv")) return -1;
+    if (!ok(hipEventRecord(ev_admit_[jn_], F_), "hipEventRecord")) return -1;
+    ++jn_;
+    did = 1;
+  }
+  return did;
+}
+
+// One batched step of every job in flight (mixed jobs, then FP64 jobs).
+int Pipeline::fine_step() {
+  if (ja_ == jn_) return 0;
+  if (freal_ >= kFDepth) {
+    const int q = query(ev_step_[freal_ % kFDepth]);
+    if (q <= 0) return q;
+  }
+  int jm = ja_;
+  while (jm < jn_ && !jobs_[jm].f64) ++jm;
+  rbc::StepRange r;
+  r.step0 = 1;
+  r.step1 = 2;
+  r.n_total = INT_MAX;   // never the last step: the next step's transform is always made
+  r.timing_index = freal_;
+  if (jm > ja_) {
+    r.slot0 = jobs_[ja_].slot;
+    r.count = jm - ja_;
+    if (!ok(rbc::launch_step_range(h_->fine, h_->wf, h_->Xring, r, nullptr, 0, 0, F_, &h_->timing), "fine step"))
+      return -1;
+  }
+  if (jn_ > jm) {
+    r.slot0 = jobs_[jm].slot;
+    r.count = jn_ - jm;
+    if (!ok(rbc::launch_step_range(h_->fine64, h_->wf64, h_->Xring, r, nullptr, 0, 0, F_), "fine step")) return -1;
+  }
+  ++t_;
+  if (want_nu_ && t_ % stride_ == 0 &&
+      !ok(rbc::launch_nusselt_ring(h_->fine, h_->Xring, jobs_[ja_].slot, jn_ - ja_, cap_, h_->meta, t_, stride_,
+                                   h_->nsf, S_, h_->nu_f, F_),
+          "nusselt"))
+    return -1;
+  while (ja_ < jn_ && jobs_[ja_].start + nf_ == t_) {
+    if (!ok(hipEventRecord(ev_done_[ja_], F_), "hipEventRecord")) return -1;
+    ++ja_;
+  }
+  if (!ok(hipEventRecord(ev_step_[freal_ % kFDepth], F_), "hipEventRecord")) return -1;
+  ++freal_;
+  return 1;
+}
+
+// Enqueues the next piece of the coarse stream: a whole copy or report
+// task, or the start or a chunk of coarse steps of a predict / correct task.
+int Pipeline::coarse_work() {
+  if (gi_ == int(tasks_.size())) return 0;
+  if (gchunks_ >= kGDepth) {
+    const int q = query(ev_chunk_[gchunks_ % kGDepth]);
+    if (q <= 0) return q;
+  }
+  const Task T = tasks_[gi_];
+  const bool g64 = T.k >= kG64_;
+  rbc::GridPlan& cp = g64 ? h_->coarse64 : h_->coarse;
+  rbc::Work& cw = g64 ? h_->wc64 : h_->wc;
+  if (gstep_ < 0) {
+    if (T.kind == kCopy) {
+      if (processed_ < T.k - 1) return 0;
+      const int j0 = job_index(T.k, T.k - 1);
+      const int j1 = (T.k <= S_ - 1) ? job_index(T.k, T.k) : -1;
+      if (ja_ <= j0 || (j1 >= 0 && jn_ <= j1)) return 0;
+      if (!ok(hipStreamWaitEvent(G_, ev_done_[j0], 0), "hipStreamWaitEvent")) return -1;
+      if (j1 >= 0 && !ok(hipStreamWaitEvent(G_, ev_admit_[j1], 0), "hipStreamWaitEvent")) return -1;
+      if (!ok(rbc::launch_combine(h_->fine, h_->coarse, 2, U_ + T.k * fs_, h_->Xring + jobs_[j0].slot * fs_, nullptr,
+                                  nullptr, h_->part + size_t(T.k) * rbc::kCombineBlocks * 2, G_),
+              "combine"))
+        return -1;
+      if (!ok(hipEventRecord(ev_task_[gi_], G_), "hipEventRecord")) return -1;
+      ++gi_;
+      return 1;
+    }
+    if (T.kind == kReport) {
+      double* pin = h_->host_pin;
+      if (T.k >= 1) {
+        if (!ok(rbc::launch_defect(h_->part, T.k, S_ + 1, h_->dscal, G_), "defect")) return -1;
+        if (!ok(hipMemcpyAsync(pin, h_->dscal, 16, hipMemcpyDeviceToHost, G_), "hipMemcpyAsync")) return -1;
+      }
+      if (want_nu_) {
+        double* nuF = pin + 2;
+        double* nuC = nuF + size_t(2) * S_ * h_->nsf * 3;
+        if (T.k == 0 && h_->nsc > 0 &&
+            !ok(hipMemcpyAsync(nuC, h_->nu_c, size_t(S_) * h_->nsc * 3 * 8, hipMemcpyDeviceToHost, G_),
+                "hipMemcpyAsync"))
+          return -1;
+        if (T.k >= 1 &&
+            !ok(hipMemcpyAsync(nuF, h_->nu_f, size_t(2) * S_ * h_->nsf * 3 * 8, hipMemcpyDeviceToHost, G_),
+                "hipMemcpyAsync"))
+          return -1;
+      }
+      if (!ok(hipEventRecord(ev_task_[gi_], G_), "hipEventRecord")) return -1;
+      pending_ = T.k;
+      ++gi_;
+      return 1;
+    }
+    if (T.kind == kCorrect) {
+      const int j = job_index(T.k, T.n);
+      const int j1 = (T.n + 1 <= S_ - 1) ? job_index(T.k, T.n + 1) : -1;
+      if (ja_ <= j || (j1 >= 0 && jn_ <= j1)) return 0;
+      if (!ok(hipStreamWaitEvent(G_, ev_done_[j], 0), "hipStreamWaitEvent")) return -1;
+      if (j1 >= 0 && !ok(hipStreamWaitEvent(G_, ev_admit_[j1], 0), "hipStreamWaitEvent")) return -1;
+    }
+    if (!ok(rbc::launch_restrict(h_->fine, cp, U_ + T.n * fs_, h_->Xc, G_), "restrict")) return -1;
+    gstep_ = 0;
+  }
+  // the first chunk (with the first transform), the chunk holding the last
+  // step and runs with Nu samples are launched directly; the rest replay
+  // the graph
+  const int C = rbc::kCoarseGraphSteps;
+  double* nu = (T.kind == kPredict && want_nu_ && h_->nu_c) ? h_->nu_c + size_t(T.n) * h_->nsc * 3 : nullptr;
+  hipGraphExec_t gx = g64 ? h_->cgraph64 : h_->cgraph;
+  if (gstep_ > 0 && !nu && gx && gstep_ + C <= nc_ - 1) {
+    if (!ok(hipGraphLaunch(gx, G_), "hipGraphLaunch")) return -1;
+    gstep_ += C;
+  } else {
+    const int c = std::min(C, nc_ - gstep_);
+    rbc::StepRange r;
+    r.slot0 = 0;
+    r.count = 1;
+    r.step0 = gstep_;
+    r.step1 = gstep_ + c;
+    r.n_total = nc_;
+    if (!ok(rbc::launch_step_range(cp, cw, h_->Xc, r, nu, h_->stride_c, h_->nsc, G_), "coarse steps")) return -1;
+    gstep_ += c;
+  }
+  if (gstep_ == nc_) {
+    const int mode = (T.kind == kPredict) ? 0 : 1;
+    const double* F = (mode == 1) ? h_->Xring + jobs_[job_index(T.k, T.n)].slot * fs_ : nullptr;
+    if (!ok(rbc::launch_combine(h_->fine, h_->coarse, mode, U_ + (T.n + 1) * fs_, F, h_->Xc, h_->Gbuf + T.n * cs_,
+                                h_->part + size_t(T.n + 1) * rbc::kCombineBlocks * 2, G_),
+            "combine"))
+      return -1;
+    if (!ok(hipEventRecord(ev_task_[gi_], G_), "hipEventRecord")) return -1;
+    ++gi_;
+    gstep_ = -1;
+  }
+  if (!ok(hipEventRecord(ev_chunk_[gchunks_ % kGDepth], G_), "hipEventRecord")) return -1;
+  ++gchunks_;
+  return 1;
+}
+
+// Reads a completed report: defect, Nu averages, the stop test and the
+// precision switch (the same rules, in the same order, as the
+// sweep-then-batch iteration).
+int Pipeline::poll_report() {
+  if (pending_ < 0) return 0;
+  const int q = query(ev_task_[report_task(pending_)]);
+  if (q <= 0) return q;
+  const int k = pending_;
+  pending_ = -1;
+  processed_ = k;
+  const double* pin = h_->host_pin;
+  const double* nuF = pin + 2;
+  const double* nuC = nuF + size_t(2) * S_ * h_->nsf * 3;
+  if (k == 0) {
+    if (want_nu_) {
+      if (h_->nsc > 0)
+        nu_average_host(h_, h_->nsc, h_->stride_c, h_->coarse.dt,
+                        [&](int n) { return nuC + size_t(n) * h_->nsc * 3; }, nu_hist_);
+      else
+        nu_hist_[0] = nu_hist_[1] = nu_hist_[2] = NAN;
+    }
+    if (K_ == 0) stop_ = true;
+    return 1;
+  }
+  defect_ = pin[0];
+  const bool bad = pin[1] != 0.0;
+  defect_hist_[k - 1] = defect_;
+  *k_done_ = k;
+  if (want_nu_) {
+    // slice n's latest run: iteration k for n >= k-1, else iteration n+1
+    const int nsf = h_->nsf;
+    nu_average_host(h_, nsf, stride_, h_->fine.dt,
+                    [&](int n) {
+                      const int par = (n >= k - 1) ? (k & 1) : ((n + 1) & 1);
+                      return nuF + (size_t(par) * S_ + n) * nsf * 3;
+                    },
+                    nu_hist_ + 3 * k);
+  }
+  if (bad) {
+    seterr(RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
+    return 1;
+  }
+  if (defect_ <= tol_ || k == K_) {
+    stop_ = true;
+    return 1;
+  }
+  if (kG64_ == INT_MAX && promote_now(h_, k, defect_, prev_, tol_)) {
+    kG64_ = k + 1;
+    kF64_ = k + 2;
+  }
+  prev_ = defect_;
+  return 1;
+}
+
+// The fine thread: admissions and batched steps until the iteration stops.
+void Pipeline::fine_loop() {
+  using clk = std::chrono::steady_clock;
+  const hipError_t e = hipSetDevice(h_->device);
+  if (e != hipSuccess) {
+    herr(e, "hipSetDevice");
+    return;
+  }
+  while (!stop_.load()) {
+    auto tp = clk::now();
+    const int a = admit();
+    const auto t1 = clk::now();
+    f_admit_s_ += std::chrono::duration<double>(t1 - tp).count();
+    if (a < 0) break;
+    const int inflight = jn_ - ja_;
+    const int b = fine_step();
+    const auto t2 = clk::now();
+    f_fine_s_ += std::chrono::duration<double>(t2 - t1).count();
+    if (b < 0) break;
+    if (b > 0) {
+      ++f_steps_;
+      runs_ += inflight;
+    }
+    if (a | b) {
+      progress_.fetch_add(1);
+      continue;
+    }
+    std::this_thread::yield();
+    f_wait_s_ += std::chrono::duration<double>(clk::now() - t2).count();
+  }
+}
+
+rbc_status Pipeline::run() {
+  using clk = std::chrono::steady_clock;
+  *k_done_ = 0;
+  rbc_status s = setup();
+  if (s != RBC_OK) return s;
+  // both streams start after the caller's work
+  RBC_HIPCHK(h_, hipEventRecord(ev_entry_, h_->stream));
+  RBC_HIPCHK(h_, hipStreamWaitEvent(F_, ev_entry_, 0));
+  RBC_HIPCHK(h_, hipStreamWaitEvent(G_, ev_entry_, 0));
+  rbc_pipeline_stats& ps = h_->pstats;
+  ps = rbc_pipeline_stats{};
+  const auto t_start = clk::now();
+  std::thread fine;
+  try {
+    fine = std::thread(&Pipeline::fine_loop, this);
+  } catch (const std::exception& ex) {
+    return fail(h_, RBC_ERR_STATE, std::string("cannot start the fine-run thread: ") + ex.what());
+  }
+  // the coarse work and the reports on this thread; a watchdog ends a
+  // schedule in which neither thread has enqueued anything for a minute
+  long seen = -1;
+  auto last = t_start;
+  while (!stop_.load()) {
+    auto tp = clk::now();
+    const int processed_before = processed_;
+    const int r = poll_report();
+    const auto t1 = clk::now();
+    ps.host_report_s += std::chrono::duration<double>(t1 - tp).count();
+    if (r < 0) break;
+    if (processed_ != processed_before && processed_ >= 0 && processed_ < 16)
+      ps.report_at_s[processed_] = std::chrono::duration<double>(t1 - t_start).count();
+    if (stop_.load()) break;
+    const int c = coarse_work();
+    const auto t2 = clk::now();
+    ps.host_coarse_s += std::chrono::duration<double>(t2 - t1).count();
+    if (c < 0) break;
+    if (c > 0) ++ps.coarse_chunks;
+    if (r | c) progress_.fetch_add(1);
+    const long pg = progress_.load();
+    if (pg != seen) {
+      seen = pg;
+      last = t2;
+    } else if (t2 - last > std::chrono::seconds(60)) {
+      seterr(RBC_ERR_STATE, "pipelined Parareal: nothing enqueued for 60 s");
+      break;
+    }
+    if (!(r | c)) {
+      std::this_thread::yield();
+      ps.host_wait_s += std::chrono::duration<double>(clk::now() - t2).count();
+    }
+  }
+  stop_.store(true);
+  fine.join();
+  // abandoned speculative work and everything enqueued finishes here
+  const hipError_t e1 = hipStreamSynchronize(F_);
+  const hipError_t e2 = hipStreamSynchronize(G_);
+  ps.wall_s = std::chrono::duration<double>(clk::now() - t_start).count();
+  ps.host_admit_s = f_admit_s_;
+  ps.host_fine_s = f_fine_s_;
+  ps.host_wait_s += f_wait_s_;
+  ps.fine_steps = f_steps_;
+  ps.mean_runs_per_step = f_steps_ ? runs_ / f_steps_ : 0.0;
+  const rbc_status st = status();
+  if (st != RBC_OK) return st;
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return fail(h_, RBC_ERR_HIP, std::string("pipelined Parareal: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  h_->k_fp64 = (kF64_ <= *k_done_) ? kF64_.load() : 0;
+  if (*k_done_ < S_ && !(defect_ <= tol_) && tol_ > 0) return RBC_NOT_CONVERGED;
+  return RBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first, double* U, const double* F, double* G,
+                            double* defect_host) {
+  if (!h || !U || !G) return fail(h, RBC_ERR_ARG, "null argument");
+  if (mode != 0 && mode != 1) return fail(h, RBC_ERR_ARG, "mode must be 0 (predict) or 1 (correct)");
+  if (mode == 1 && !F) return fail(h, RBC_ERR_ARG, "F is NULL in correct mode");
+  if (first < 0 || first > h->p.n_slices) return fail(h, RBC_ERR_ARG, "first_slice out of range");
+  rbc_status s = sweep(h, mode, first, U, F, G, false);
+  if (s != RBC_OK) return s;
+  if (defect_host) {
+    bool bad = false;
+    if ((s = read_defect(h, first + 1, h->p.n_slices + 1, defect_host, &bad)) != RBC_OK) return s;
+    if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in the coarse sweep");
+  }
+  return RBC_OK;
+}
+
+rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, int32_t* k_done,
+                            double* defect_hist, double* nu_hist) {
+  if (!h || !U || !k_done || !defect_hist) return fail(h, RBC_ERR_ARG, "null argument");
+  if (k_max < 0) return fail(h, RBC_ERR_ARG, "k_max < 0");
+  h->k_fp64 = 0;
+  if (!h->p.pipelined) return parareal_sequential(h, U, k_max, tol, k_done, defect_hist, nu_hist);
+  const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
+  Pipeline pl(h, U, std::min<int>(k_max, h->p.n_slices), tol, want_nu, k_done, defect_hist, nu_hist);
+  return pl.run();
+}
+
+rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out) {
+  if (!h || !out) return fail(h, RBC_ERR_ARG, "null argument");
+  *out = h->pstats;
+  return RBC_OK;
+}
+
+rbc_status rbc_fine_fp64_from(rbc_handle h, int32_t* k) {
+  if (!h || !k) return fail(h, RBC_ERR_ARG, "null argument");
+  *k = h->k_fp64;
+  return RBC_OK;
+}
+
+}  // extern "C"

@@ -50,6 +50,19 @@ class rbc_params(ctypes.Structure):
         ("nu_t_start", ctypes.c_double),
         ("T_bot", ctypes.c_double), ("T_top", ctypes.c_double),
         ("promote_fp64", ctypes.c_int32),
+        ("pipelined", ctypes.c_int32),
+    ]
+
+
+class rbc_pipeline_stats(ctypes.Structure):
+    _fields_ = [
+        ("wall_s", ctypes.c_double),
+        ("host_admit_s", ctypes.c_double), ("host_fine_s", ctypes.c_double),
+        ("host_coarse_s", ctypes.c_double), ("host_report_s", ctypes.c_double),
+        ("host_wait_s", ctypes.c_double),
+        ("fine_steps", ctypes.c_int64), ("coarse_chunks", ctypes.c_int64),
+        ("mean_runs_per_step", ctypes.c_double),
+        ("report_at_s", ctypes.c_double * 16),
     ]
 
 
@@ -77,6 +90,7 @@ def _load():
         "rbc_kernel_timing_enable": (st, [vp, i32, i32]),
         "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64)]),
         "rbc_synchronize": (st, [vp]),
+        "rbc_get_pipeline_stats": (st, [vp, P(rbc_pipeline_stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -200,6 +214,15 @@ def rbc_kernel_timing(h) -> Tuple[float, int]:
 
 def rbc_synchronize(h) -> None:
     _check(_lib.rbc_synchronize(h), h)
+
+
+def rbc_get_pipeline_stats(h) -> dict:
+    """Scheduler statistics of the last pipelined parareal_iterate."""
+    out = rbc_pipeline_stats()
+    _check(_lib.rbc_get_pipeline_stats(h, ctypes.byref(out)), h)
+    d = {name: getattr(out, name) for name, _ in rbc_pipeline_stats._fields_ if name != "report_at_s"}
+    d["report_at_s"] = list(out.report_at_s)
+    return d
 
 
 def params_from_workload(w, **overrides) -> rbc_params:
