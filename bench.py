@@ -7,17 +7,23 @@ slices over t in [0, 50], fine step 2e-4 (7813 steps per slice), coarse grid
 128 x 32 at step 2e-3, ARS(4,4,3), mixed precision (FP32 transforms and
 products, FP64 state, solves, correction, defect and Nusselt numbers).
 
-One timed step is one Parareal iteration with every slice active: the fine
-propagator on all 32 slices over their whole slice (with Nusselt samples
-every 50 fine steps), then the serial coarse correction sweep, the
-correction U_{n+1} = G(U_n^new) + F(U_n^old) - G(U_n^old) and the defect.
-`value` is fine DOF-steps (grid points x slices x fine steps) per second of
-the whole iteration's wall time, so the coarse sweep counts against it.
+One timed step is one Parareal iteration.  The timed region is one whole
+Parareal run from the seeded initial state: the coarse prediction, then
+`--steps` iterations in the pipelined schedule (each slice's fine run starts
+as soon as its initial state is corrected and advances in one batch with
+every other run in flight; the serial coarse sweep overlaps them), with the
+correction U_{n+1} = G(U_n^new) + F(U_n^old) - G(U_n^old), the defect and
+Nusselt samples every 50 fine steps.  Iteration k runs F on slices k-1..S-1.
+`value` is the fine DOF-steps computed (grid points x fine steps x fine
+runs) per second of that wall time, so the coarse sweeps count against it.
+The same run in the sweep-then-batch order (bit-identical results) and the
+fine propagator alone at full batch are reported beside it.
 
 The roofline object describes the dominant kernel (the per-mode stage
-kernel): algorithmic bytes per launch from the byte model below, divided
-by its mean launch duration measured with HIP events on the library's
-stream during the timed steps.  The cpu_baseline object times the FP64
+kernel): algorithmic bytes per launch from the byte model below (per state
+times the mean number of states in the timed launches), divided by its
+mean launch duration measured with HIP events on the stream it runs on
+during the timed run.  The cpu_baseline object times the FP64
 CPU oracle on one host core over a bounded number of fine steps of one slice.
 """
 from __future__ import annotations
@@ -111,10 +117,11 @@ def cpu_baseline(w, seconds: float):
 
 
 def time_to_solution(w, tol: float = 1e-8):
-    """Parareal (this workload's precision, all slices batched) to a defect
-    <= tol, against the serial FP64 fine stepper on one run over the same
-    horizon and fine step.  Both report time-averaged Nusselt numbers over the
-    whole horizon (samples every NU_STRIDE fine steps)."""
+    """Parareal (this workload's precision with the FP64 switch, pipelined
+    schedule) to a defect <= tol, against the serial FP64 fine stepper on one
+    run over the same horizon and fine step.  Both report time-averaged
+    Nusselt numbers over the whole horizon (samples every NU_STRIDE fine
+    steps)."""
     import torch
 
     from paper_2001_01609_amd import rbc as R
@@ -135,6 +142,7 @@ def time_to_solution(w, tol: float = 1e-8):
         torch.cuda.synchronize()
         t_para = time.perf_counter() - t0
         k64 = R.rbc_fine_fp64_from(h)
+        report_at = R.rbc_get_pipeline_stats(h)["report_at_s"][: kd + 1] if p.pipelined else None
         u_end = U[S * n:].clone()
     finally:
         R.rbc_destroy(h)
@@ -160,7 +168,8 @@ def time_to_solution(w, tol: float = 1e-8):
         R.rbc_destroy(h)
     nu_par = nu[-1]
     return {"parareal_s": t_para, "serial_fp64_s": t_ser, "speedup": t_ser / t_para,
-            "iterations": kd, "fp64_from_iteration": k64, "status": status, "tol": tol, "defects": [float(d) for d in defects],
+            "iterations": kd, "fp64_from_iteration": k64, "iteration_done_at_s": report_at,
+            "status": status, "tol": tol, "defects": [float(d) for d in defects],
             "serial_steps": ns, "nu_avg_parareal": [float(v) for v in nu_par],
             "nu_avg_serial_fp64": [float(v) for v in nu_ser],
             "nu_V_rel_diff": float(abs(nu_par[0] - nu_ser[0]) / abs(nu_ser[0])),
@@ -195,26 +204,17 @@ def main() -> int:
     w = I.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0)
-    h = R.rbc_create(p, stream.cuda_stream)
     S = w.n_slices
+    K = args.steps
+    # the measured configuration: mixed precision throughout (no FP64 switch),
+    # Nu samples every NU_STRIDE fine steps, pipelined schedule
+    p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0, pipelined=1)
+    h = R.rbc_create(p, stream.cuda_stream)
     try:
         n = R.rbc_state_size(h, 0)
-        nc = R.rbc_state_size(h, 1)
         nf, dtf = R.rbc_steps_per_slice(h, 0)
         ncs, dtc = R.rbc_steps_per_slice(h, 1)
         U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
-        F = torch.zeros(S * n, dtype=torch.float64, device=dev)
-        G = torch.zeros(S * nc, dtype=torch.float64, device=dev)
-        nu = torch.zeros(S * (nf // NU_STRIDE) * 3, dtype=torch.float64, device=dev)
-        R.rbc_init_state(h, w.seed, w.noise_amp, U)
-        # realistic slice-start states: the coarse prediction (untimed)
-        R.rbc_coarse_sweep(h, 0, 0, U, None, G)
-        torch.cuda.synchronize()
-
-        def iteration():
-            R.rbc_fine_step_batch(h, U, F, S, nf, nu)
-            return R.rbc_coarse_sweep(h, 1, 0, U, F, G, want_defect=True)
 
         def calibrate():
             if args.calibrate_copy > 0:
@@ -225,58 +225,87 @@ def main() -> int:
                 del a, b
 
         if args.profile_steps > 0:
-            R.rbc_fine_step_batch(h, U, F, S, args.profile_steps, None)
+            # the fine propagator's kernels at full batch from the seeded state
+            F = torch.zeros(S * n, dtype=torch.float64, device=dev)
+            R.rbc_init_state(h, w.seed, w.noise_amp, F)
+            F.view(S, n)[1:] = F.view(S, n)[0]
+            R.rbc_fine_step_batch(h, F, F, S, args.profile_steps, None)
             torch.cuda.synchronize()
             calibrate()
             print(f"[bench] profile mode: {args.profile_steps} batched fine steps done", file=sys.stderr)
             return 0
 
-        for it in range(args.warmup):
-            iteration()
+        def parareal(k):
+            U.zero_()
+            R.rbc_init_state(h, w.seed, w.noise_amp, U)
             torch.cuda.synchronize()
-            print(f"[bench] warmup iteration {it + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, kd, defects, nu = R.parareal_iterate(h, U, k, 0.0, want_nu=True)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, kd, defects, nu
+
+        for it in range(args.warmup):
+            parareal(1)
+            print(f"[bench] warmup Parareal run {it + 1}/{args.warmup} (1 iteration) done", file=sys.stderr,
+                  flush=True)
         R.rbc_kernel_timing_enable(h, 0, TIMING_EVERY)
-        defects = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for it in range(args.steps):
-            defects.append(iteration())
-            print(f"[bench] timed iteration {it + 1}/{args.steps} done", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        k_ms, k_cnt = R.rbc_kernel_timing(h)
+        el, kd, defects, nu_hist = parareal(K)
+        k_ms, k_cnt, k_batch = R.rbc_kernel_timing(h)
         R.rbc_kernel_timing_enable(h, -1, 0)
-        # fine propagator alone (events around one batched F call)
+        pstats = R.rbc_get_pipeline_stats(h)
+        print(f"[bench] timed pipelined Parareal: {K} iterations in {el:.2f} s", file=sys.stderr, flush=True)
+        u_pipe = U.cpu().numpy()
+        finite = bool(np.isfinite(u_pipe).all())
+        # fine propagator alone at full batch (events around one batched F
+        # call; the stage kernel timed inside it as well)
+        F = U[:S * n].clone()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        R.rbc_kernel_timing_enable(h, 0, TIMING_EVERY)
         e0.record(stream)
-        R.rbc_fine_step_batch(h, U, F, S, nf, nu)
+        R.rbc_fine_step_batch(h, F, F, S, nf, None)
         e1.record(stream)
         torch.cuda.synchronize()
         f_ms = e0.elapsed_time(e1)
+        kf_ms, kf_cnt, kf_batch = R.rbc_kernel_timing(h)
+        R.rbc_kernel_timing_enable(h, -1, 0)
         calibrate()
-        nu_host = nu.view(S, -1, 3).cpu().numpy()
-        finite = bool(np.isfinite(U.cpu().numpy()).all())
+    finally:
+        R.rbc_destroy(h)
+    # the same K iterations in the sweep-then-batch order (same results, bit for bit)
+    q = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0, pipelined=0)
+    h = R.rbc_create(q, stream.cuda_stream)
+    try:
+        U.zero_()
+        R.rbc_init_state(h, w.seed, w.noise_amp, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R.parareal_iterate(h, U, K, 0.0, want_nu=True)
+        torch.cuda.synchronize()
+        el_seq = time.perf_counter() - t0
+        same = bool(np.array_equal(U.cpu().numpy(), u_pipe))
+        print(f"[bench] sweep-then-batch Parareal: {K} iterations in {el_seq:.2f} s", file=sys.stderr, flush=True)
     finally:
         R.rbc_destroy(h)
 
     dof = w.Nx * w.Nz
-    fine_dof_steps = dof * S * nf
-    ms_step = 1e3 * el / args.steps
-    value = fine_dof_steps * args.steps / el
+    runs = sum(S - k + 1 for k in range(1, K + 1))      # fine runs of iterations 1..K
+    fine_dof_steps = dof * nf * runs
+    value = fine_dof_steps / el
     rb = 4 if w.mixed else 8
     s = w.scheme
-    per_launch = stage_kernel_bytes_per_dof_step(s, rb) / s * dof * S
+    per_launch = stage_kernel_bytes_per_dof_step(s, rb) / s * dof * k_batch
     achieved = per_launch / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    full_launch = stage_kernel_bytes_per_dof_step(s, rb) / s * dof * kf_batch
+    achieved_full = full_launch / (kf_ms * 1e-3) / 1e9 if kf_ms > 0 else 0.0
     traffic = measured_traffic(w.name)
     out = {
         "metric": "fine-step DOF-steps/s (%HBM roofline); Parareal vs serial time-to-solution",
         "value": value,
         "unit": "DOF-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": 1e3 * el / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -284,17 +313,27 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "Ra": w.Ra, "Pr": w.Pr, "grid": [w.Nx, w.Nz],
                    "coarse_grid": [w.Nx_c, w.Nz_c], "slices": S, "t": [w.t0, w.t_end],
-                   "fine_steps_per_slice": nf, "coarse_steps_per_slice": ncs, "scheme": "ARS443" if s == 4 else "ARS222",
-                   "step": "one Parareal iteration, all slices active"},
+                   "fine_steps_per_slice": nf, "coarse_steps_per_slice": ncs,
+                   "scheme": "ARS443" if s == 4 else "ARS222",
+                   "step": "one Parareal iteration (pipelined schedule; the timed run is the coarse "
+                           "prediction and `steps` iterations from the seeded state, fine runs of "
+                           "iteration k on slices k-1..S-1)"},
         "roofline": {"bound": "hbm", "kernel": "stage_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": per_launch, "mean_launch_ms": k_ms, "timed_launches": k_cnt},
-        "fine_propagator": {"dof_steps_per_s": fine_dof_steps / (f_ms * 1e-3), "ms_per_call": f_ms,
-                            "us_per_batched_step": 1e3 * f_ms / nf,
+                     "bytes_per_launch": per_launch, "mean_launch_ms": k_ms, "timed_launches": k_cnt,
+                     "mean_slices_per_launch": k_batch},
+        "fine_propagator": {"dof_steps_per_s": dof * S * nf / (f_ms * 1e-3), "ms_per_call": f_ms,
+                            "us_per_batched_step": 1e3 * f_ms / nf, "slices": S,
+                            "stage_kernel": {"mean_launch_ms": kf_ms, "timed_launches": kf_cnt,
+                                             "bytes_per_launch": full_launch, "achieved_gbs": achieved_full,
+                                             "frac": achieved_full / HBM_PEAK_GBS},
                             "bytes_per_dof_step_model": stage_kernel_bytes_per_dof_step(s, rb) +
                             xpass_bytes_per_dof_step(s, rb)},
-        "parareal": {"defects": defects, "nu_mean_last": [float(v) for v in nu_host.reshape(-1, 3).mean(0)],
-                     "finite": finite},
+        "parareal": {"iterations": kd, "defects": [float(d) for d in defects], "fine_runs": runs,
+                     "nu_avg_last": [float(v) for v in nu_hist[-1]], "finite": finite,
+                     "sweep_then_batch_s": el_seq, "sweep_then_batch_value": fine_dof_steps / el_seq,
+                     "pipelined_speedup": el_seq / el, "bitwise_equal_to_sweep_then_batch": same,
+                     "scheduler": {k: v for k, v in pstats.items() if k != "report_at_s"}},
     }
     if not args.no_tts:
         out["time_to_solution"] = time_to_solution(w)

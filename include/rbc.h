@@ -209,14 +209,17 @@ rbc_status rbc_nusselt(rbc_handle h, const double* U_dev, int32_t n_states, doub
  * -S1S0 N_T, for the equation rows (the last 4 / 2 rows are zero). */
 rbc_status rbc_explicit_terms(rbc_handle h, const double* U_dev, double* E_dev);
 
-/* Kernel timing with HIP events on the handle's stream (tracing).
- * kernel 0 = the per-mode stage kernel, 1 = the x-pass, -1 = off.  While
- * enabled, on every `every`-th fine step each launch of that kernel is
+/* Kernel timing with HIP events (tracing) of the fine grid's kernels, on
+ * the stream they run on (the handle's stream, or the fine-run stream of a
+ * pipelined parareal_iterate).  kernel 0 = the per-mode stage kernel, 1 =
+ * the x-pass, -1 = off.  While enabled, on every `every`-th batched fine
+ * step of the working-precision fine plan each launch of that kernel is
  * bracketed by an event pair (at most 8192 pairs are kept).
- * rbc_kernel_timing synchronises, returns the mean duration in ms and the
- * number of timed launches, and clears the record. */
+ * rbc_kernel_timing synchronises, returns the mean duration in ms, the
+ * number of timed launches and (if mean_batch is not NULL) the mean number
+ * of states per timed launch, and clears the record. */
 rbc_status rbc_kernel_timing_enable(rbc_handle h, int32_t kernel, int32_t every);
-rbc_status rbc_kernel_timing(rbc_handle h, double* mean_ms, int64_t* count);
+rbc_status rbc_kernel_timing(rbc_handle h, double* mean_ms, int64_t* count, double* mean_batch);
 
 /* Wait for all work enqueued on the handle's stream. */
 rbc_status rbc_synchronize(rbc_handle h);

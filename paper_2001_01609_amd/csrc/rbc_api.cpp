@@ -387,10 +387,11 @@ rbc_status rbc_kernel_timing_enable(rbc_handle h, int32_t kernel, int32_t every)
   h->timing.kernel = kernel;
   h->timing.every = (kernel < 0) ? 0 : every;
   h->timing.used = 0;
+  h->timing.units = 0;
   return RBC_OK;
 }
 
-rbc_status rbc_kernel_timing(rbc_handle h, double* mean_ms, int64_t* count) {
+rbc_status rbc_kernel_timing(rbc_handle h, double* mean_ms, int64_t* count, double* mean_batch) {
   if (!h || !mean_ms || !count) return fail(h, RBC_ERR_ARG, "null argument");
   HIPCHK(h, hipStreamSynchronize(h->stream));
   double tot = 0;
@@ -403,7 +404,9 @@ rbc_status rbc_kernel_timing(rbc_handle h, double* mean_ms, int64_t* count) {
   }
   *mean_ms = n ? tot / n : 0.0;
   *count = n;
+  if (mean_batch) *mean_batch = n ? h->timing.units / n : 0.0;
   h->timing.used = 0;
+  h->timing.units = 0;
   return RBC_OK;
 }
 

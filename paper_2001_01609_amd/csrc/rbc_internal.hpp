@@ -107,6 +107,7 @@ struct KernelTiming {
   int every = 0;
   std::vector<hipEvent_t> ev;   // pairs: start, stop
   size_t used = 0;              // events in use
+  double units = 0;             // states (slices) processed by the timed launches
   static constexpr size_t kMaxPairs = 8192;
 };
 

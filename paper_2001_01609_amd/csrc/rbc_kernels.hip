@@ -1343,6 +1343,7 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, const StepRange& r,
       for (int j = 1; j <= i; ++j) b.hai[j] = g.dt * tb.ai[i][j];
       b.haii = g.dt * tb.ai[i][i];
       if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
+      if (timed) tm->units += r.count;
       if ((e = run_stage<Real>(g, w, b, X, r.count, nullptr, st)) != hipSuccess) return e;
       if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
     }

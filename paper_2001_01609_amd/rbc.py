@@ -88,7 +88,7 @@ def _load():
         "rbc_fine_fp64_from": (st, [vp, P(i32)]),
         "rbc_explicit_terms": (st, [vp, vp, vp]),
         "rbc_kernel_timing_enable": (st, [vp, i32, i32]),
-        "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64)]),
+        "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64), P(dbl)]),
         "rbc_synchronize": (st, [vp]),
         "rbc_get_pipeline_stats": (st, [vp, P(rbc_pipeline_stats)]),
     }
@@ -206,10 +206,11 @@ def rbc_kernel_timing_enable(h, kernel: int, every: int) -> None:
     _check(_lib.rbc_kernel_timing_enable(h, kernel, every), h)
 
 
-def rbc_kernel_timing(h) -> Tuple[float, int]:
-    ms, n = ctypes.c_double(), ctypes.c_int64()
-    _check(_lib.rbc_kernel_timing(h, ctypes.byref(ms), ctypes.byref(n)), h)
-    return ms.value, n.value
+def rbc_kernel_timing(h) -> Tuple[float, int, float]:
+    """(mean launch ms, timed launches, mean states per timed launch)."""
+    ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(_lib.rbc_kernel_timing(h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)), h)
+    return ms.value, n.value, b.value
 
 
 def rbc_synchronize(h) -> None:
