@@ -17,7 +17,10 @@ What it computes (each function names the part of the paper it follows):
   named in sections 3.2 and 3.6 (ARS(2,2,2) and ARS(4,4,3)): diffusion and
   buoyancy implicit, advection explicit; each stage solve is a dense LU
   with partial pivoting of the tau-modified ultraspherical system;
-* the Nusselt numbers of section 2.2 (Eqs. 8-10);
+* the Nusselt numbers of section 2.2 (Eqs. 8-10) and the other quantities
+  of its consistency checks: the Reynolds number from the RMS velocity, the
+  spread Nu_int of the three Nusselt numbers (Eq. 11), and the buoyancy
+  production P against the viscous dissipation epsilon_U (Eq. 12);
 * the Parareal iteration of section 3.1 (Eq. 13), serially, with a coarse
   propagator built by spatial coarsening and a larger step (section 3.6).
 
@@ -536,6 +539,69 @@ def kinetic_energy(g: Grid, X: State) -> float:
         f = np.fft.irfft(H, n=g.Nx, axis=0)
         tot += 0.25 * np.sum(wl * np.mean(f * f, axis=0))
     return tot
+
+
+def _volume_mean_sq(g: Grid, fields) -> float:
+    """Volume mean of the sum of squares of real fields given by their
+    spectral coefficients (mode m, Chebyshev n): Nx-point mean in x,
+    Gauss-Legendre quadrature in z exact for the squared polynomials."""
+    zl, wl = np.polynomial.legendre.leggauss(g.Nz + 2)
+    V = np.cos(np.outer(np.arccos(zl), np.arange(g.Nz)))
+    tot = 0.0
+    for c in fields:
+        H = np.zeros((g.Nx // 2 + 1, len(zl)), dtype=np.complex128)
+        H[: g.Mx] = (c @ V.T) * g.Nx
+        f = np.fft.irfft(H, n=g.Nx, axis=0)
+        tot += 0.5 * np.sum(wl * np.mean(f * f, axis=0))
+    return tot
+
+
+def viscous_dissipation(g: Grid, X: State) -> float:
+    """epsilon_U of section 2.2 in free-fall units: nu times the volume mean
+    of |grad u|^2 = u_x^2 + u_z^2 + w_x^2 + w_z^2 (all four components
+    written out).  Dotting the momentum equation with u and averaging gives
+    d(KE)/dt = P - epsilon_U for no-slip, periodic boundaries."""
+    u, w, *_ = velocity_fields(g, X)
+    k = g.k[:, None]
+    grads = (1j * k * u, cheb_deriv(u, g.scale), 1j * k * w, cheb_deriv(w, g.scale))
+    return g.nu * _volume_mean_sq(g, grads)
+
+
+def buoyancy_production(g: Grid, X: State) -> float:
+    """P of section 2.2 in free-fall units (buoyancy coefficient 1): the
+    volume mean of w T."""
+    psi = X.P.copy()
+    psi[0] = 0.0
+    w_hat = -1j * g.k[:, None] * psi
+    zl, wl = np.polynomial.legendre.leggauss(g.Nz)
+    V = np.cos(np.outer(np.arccos(zl), np.arange(g.Nz)))
+
+    def phys(c):
+        H = np.zeros((g.Nx // 2 + 1, g.Nz), dtype=np.complex128)
+        H[: g.Mx] = (c @ V.T) * g.Nx
+        return np.fft.irfft(H, n=g.Nx, axis=0)
+
+    return 0.5 * np.sum(wl * np.mean(phys(w_hat) * phys(X.T), axis=0))
+
+
+def diagnostics(g: Grid, X: State) -> np.ndarray:
+    """The per-state record (Nu_V, Nu_b, Nu_t, KE, epsilon_U, P)."""
+    nu_v, nu_b, nu_t = nusselt(g, X)
+    return np.array([nu_v, nu_b, nu_t, kinetic_energy(g, X), viscous_dissipation(g, X),
+                     buoyancy_production(g, X)])
+
+
+def time_averages(g: Grid, samples: np.ndarray) -> np.ndarray:
+    """Time averages of section 2.2 over records (Nu_V, Nu_b, Nu_t, KE,
+    epsilon_U, P): (Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, epsilon_U, P,
+    |P - epsilon_U| / P).  Re is the time average of the RMS velocity
+    <u^2 + w^2>^(1/2) over the viscosity (free-fall velocity, height 1);
+    Nu_int is Eq. 11 on the averaged Nusselt numbers."""
+    s = np.asarray(samples, dtype=np.float64).reshape(-1, 6)
+    nv, nb, nt, ke, eps, P = s.mean(axis=0)
+    re = np.mean(np.sqrt(2.0 * s[:, 3])) / g.nu
+    nu_int = max(abs(nb - nv), abs(nb - nt), abs(nv - nt)) / nv
+    return np.array([nv, nb, nt, nu_int, ke, re, eps, P, abs(P - eps) / P])
 
 
 # --------------------------------------------------------------------------

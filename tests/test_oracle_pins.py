@@ -483,3 +483,86 @@ def test_kinetic_energy_closed_form():
     I2, _ = scipy.integrate.quad(lambda s: gfun(s) ** 2, 0, 1, epsabs=1e-15)
     want = b * b / 4 * (I1 + k * k * I2) + c * c / 4
     assert abs(O.kinetic_energy(g_, X) - want) < 1e-13
+
+
+# ------------------------------------- consistency checks of section 2.2 ---
+
+def test_viscous_dissipation_closed_form():
+    """psi = b sin(kx) g(z), g = z^2 (1-z)^2, and u_bar = c sin(pi z):
+    <|grad u|^2> = b^2/2 int (g''^2 + 2 k^2 g'^2 + k^4 g^2) + c^2 pi^2 / 2,
+    epsilon_U = nu times that."""
+    b, c = 0.07, 0.03
+    g_ = O.Grid(1e5, 1.0, 2.0, 1.0, 16, 32, 1.0)
+    k = g_.k[1]
+    x, z = O.grid_points(g_)
+    psi = b * np.sin(k * x)[:, None] * (z * z * (1 - z) ** 2)[None, :]
+    X = O.State(np.zeros((g_.Mx, g_.Nz), complex), O.from_grid(psi, g_.Mx, g_.Nz))
+    X.P[0] = _cheb_of(lambda s: c * np.sin(np.pi * s), g_.Lz, g_.Nz)
+    gp = np.polynomial.Polynomial([0, 0, 1, -2, 1])          # z^2 (1-z)^2, integrated exactly
+    q = lambda f: (f * f).integ()(1.0)
+    want = b * b / 2 * (q(gp.deriv(2)) + 2 * k * k * q(gp.deriv(1)) + k ** 4 * q(gp)) + c * c * np.pi ** 2 / 2
+    got = O.viscous_dissipation(g_, X)
+    assert abs(got / g_.nu - want) < 1e-12 * want, (got / g_.nu, want)
+
+
+def test_buoyancy_production_closed_form():
+    """T = 1 - z + a z(1-z) + e cos(kx) sin(pi z), psi = b sin(kx) g(z):
+    P = <w T> = -(e b k / 2) int g sin(pi z)."""
+    a, e, b = 0.2, 0.05, 0.03
+    g = O.Grid(1e5, 1.0, 2.0, 1.0, 16, 32, 1.0)
+    k = g.k[1]
+    x, z = O.grid_points(g)
+    T = (1 - z + a * z * (1 - z))[None, :] + e * np.cos(k * x)[:, None] * np.sin(np.pi * z)[None, :]
+    psi = b * np.sin(k * x)[:, None] * (z * z * (1 - z) ** 2)[None, :]
+    X = O.State(O.from_grid(T, g.Mx, g.Nz), O.from_grid(psi, g.Mx, g.Nz))
+    X.P[0] = 0
+    I_, _ = scipy.integrate.quad(lambda s: s * s * (1 - s) ** 2 * np.sin(np.pi * s), 0, 1,
+                                 epsabs=1e-15, epsrel=1e-14)
+    assert abs(O.buoyancy_production(g, X) - (-e * b * k / 2) * I_) < 1e-15
+
+
+def _convecting_state(steps=300):
+    g = O.Grid(3e3, 1.0, 2.0, 1.0, 32, 16, 0.01)
+    X = O.initial_state(g, I.gaussian_noise(5, g.Nx, g.Nz), 0.3)
+    return g, O.Stepper(g), O.Stepper(g).run(X, steps)
+
+
+def test_dissipation_equals_enstrophy_for_no_slip_fields():
+    """For a divergence-free field vanishing on the walls and periodic in x,
+    <|grad u|^2> = <omega^2> (the difference integrates to boundary terms)."""
+    g, _, X = _convecting_state()
+    u, w, *_ = O.velocity_fields(g, X)
+    psi = X.P.copy()
+    psi[0] = 0
+    om = O.cheb_deriv(O.cheb_deriv(psi, g.scale), g.scale) - (g.k[:, None] ** 2) * psi
+    om[0] = O.cheb_deriv(X.P[0].real, g.scale)
+    enstrophy = O._volume_mean_sq(g, (om,))
+    eps = O.viscous_dissipation(g, X)
+    assert abs(eps / g.nu - enstrophy) < 1e-12 * enstrophy
+
+
+def test_energy_budget_matches_time_derivative():
+    """d(KE)/dt = P - epsilon_U along the time-stepped solution (central
+    difference over two steps of the fourth-order-in-space, third-order-in-
+    time integration; the signs and factors of P and epsilon_U are those of
+    the equations actually solved)."""
+    g, st, Xm = _convecting_state()
+    X0 = st.step(Xm)
+    Xp = st.step(X0)
+    dke = (O.kinetic_energy(g, Xp) - O.kinetic_energy(g, Xm)) / (2 * g.dt)
+    budget = O.buoyancy_production(g, X0) - O.viscous_dissipation(g, X0)
+    assert abs(dke - budget) < 1e-4 * abs(budget), (dke, budget)
+
+
+def test_time_averages_of_the_consistency_checks():
+    """Eq. 11 and the balance of Eq. 12 on hand-made records; Re is the mean
+    RMS velocity over the viscosity."""
+    g = O.Grid(1e6, 1.0, 2.0, 1.0, 16, 8, 1.0)
+    s = np.array([[8.0, 7.9, 8.2, 0.02, 0.0070, 0.0071],
+                  [8.2, 8.1, 8.0, 0.08, 0.0072, 0.0071]])
+    a = O.time_averages(g, s)
+    assert np.allclose(a[:3], [8.1, 8.0, 8.1])
+    assert abs(a[3] - 0.1 / 8.1) < 1e-15
+    assert abs(a[4] - 0.05) < 1e-15
+    assert abs(a[5] - (0.2 + 0.4) / 2 / g.nu) < 1e-12 * a[5]
+    assert np.allclose(a[6:8], [0.0071, 0.0071]) and a[8] < 1e-12
