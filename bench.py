@@ -116,6 +116,21 @@ def cpu_baseline(w, seconds: float):
                       f"from the seeded initial state; {el:.1f} s on one thread"}
 
 
+def q_visc(w) -> float:
+    """Viscosity in free-fall units."""
+    return math.sqrt(w.Pr / w.Ra)
+
+
+def diag_time_averages(rec: np.ndarray, visc: float) -> np.ndarray:
+    """Time averages of diagnostic records (Nu_V, Nu_b, Nu_t, KE, eps_U, P)
+    in the library's order: Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, eps_U, P,
+    |P - eps_U| / P (section 2.2)."""
+    nv, nb, nt, ke, eps, P = rec.mean(axis=0)
+    re = float(np.mean(np.sqrt(2.0 * rec[:, 3]))) / visc
+    nu_int = max(abs(nb - nv), abs(nb - nt), abs(nv - nt)) / nv
+    return np.array([nv, nb, nt, nu_int, ke, re, eps, P, abs(P - eps) / P])
+
+
 def time_to_solution(w, tol: float = 1e-8):
     """Parareal (this workload's precision with the FP64 switch, pipelined
     schedule) to a defect <= tol, against the serial FP64 fine stepper on one
@@ -155,23 +170,25 @@ def time_to_solution(w, tol: float = 1e-8):
         ns, dts = R.rbc_steps_per_slice(h, 0)
         V = torch.zeros(n, dtype=torch.float64, device=dev)
         R.rbc_init_state(h, w.seed, w.noise_amp, V)
-        nus = torch.zeros((ns // NU_STRIDE) * 3, dtype=torch.float64, device=dev)
+        nus = torch.zeros((ns // NU_STRIDE) * R.RBC_DIAG, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         print(f"[bench] time to solution: serial FP64 ({ns} steps)", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         R.rbc_fine_step_batch(h, V, V, 1, ns, nus)
         torch.cuda.synchronize()
         t_ser = time.perf_counter() - t0
-        nu_ser = nus.view(-1, 3).mean(0).cpu().numpy()
+        nu_ser = diag_time_averages(nus.view(-1, R.RBC_DIAG).cpu().numpy(), q_visc(w))
         rel = float(torch.linalg.norm(u_end - V) / torch.linalg.norm(V))
     finally:
         R.rbc_destroy(h)
     nu_par = nu[-1]
+    fields = R.DIAG_AVG_FIELDS
     return {"parareal_s": t_para, "serial_fp64_s": t_ser, "speedup": t_ser / t_para,
             "iterations": kd, "fp64_from_iteration": k64, "iteration_done_at_s": report_at,
             "status": status, "tol": tol, "defects": [float(d) for d in defects],
-            "serial_steps": ns, "nu_avg_parareal": [float(v) for v in nu_par],
-            "nu_avg_serial_fp64": [float(v) for v in nu_ser],
+            "serial_steps": ns,
+            "averages_parareal": {f: float(v) for f, v in zip(fields, nu_par)},
+            "averages_serial_fp64": {f: float(v) for f, v in zip(fields, nu_ser)},
             "nu_V_rel_diff": float(abs(nu_par[0] - nu_ser[0]) / abs(nu_ser[0])),
             "final_state_rel_l2_vs_serial_fp64": rel}
 
@@ -330,7 +347,8 @@ def main() -> int:
                             "bytes_per_dof_step_model": stage_kernel_bytes_per_dof_step(s, rb) +
                             xpass_bytes_per_dof_step(s, rb)},
         "parareal": {"iterations": kd, "defects": [float(d) for d in defects], "fine_runs": runs,
-                     "nu_avg_last": [float(v) for v in nu_hist[-1]], "finite": finite,
+                     "averages_last": {f: float(v) for f, v in zip(R.DIAG_AVG_FIELDS, nu_hist[-1])},
+                     "finite": finite,
                      "sweep_then_batch_s": el_seq, "sweep_then_batch_value": fine_dof_steps / el_seq,
                      "pipelined_speedup": el_seq / el, "bitwise_equal_to_sweep_then_batch": same,
                      "scheduler": {k: v for k, v in pstats.items() if k != "report_at_s"}},

@@ -59,6 +59,25 @@ typedef enum {
 } rbc_status;
 
 typedef enum { RBC_FP64 = 0, RBC_MIXED = 1 } rbc_precision;
+
+/* Diagnostic record of one state (section 2.2), RBC_DIAG doubles:
+ *   Nu_V (Eq. 8), Nu_b (Eq. 9), Nu_t (Eq. 10), KE = <u^2 + w^2>/2,
+ *   epsilon_U = nu <|grad u|^2> (viscous dissipation), P = <w T> (buoyancy
+ *   production), all volume means in free-fall units, exact for the
+ *   discrete fields.  Time averages, RBC_DIAG_AVG doubles:
+ *   Nu_V, Nu_b, Nu_t, Nu_int (Eq. 11, on the averaged Nusselt numbers), KE,
+ *   Re (mean of <u^2 + w^2>^(1/2) over the viscosity), epsilon_U, P,
+ *   |P - epsilon_U| / P (the balance check of Eq. 12). */
+#define RBC_DIAG 6
+#define RBC_DIAG_AVG 9
+
+/* Why the last parareal_iterate stopped. */
+typedef enum {
+  RBC_STOP_DEFECT = 0,      /* defect <= tol                                   */
+  RBC_STOP_STATISTICS = 1,  /* time-averaged Nusselt numbers settled (stat_tol) */
+  RBC_STOP_KMAX = 2,        /* k_max iterations                                */
+  RBC_STOP_EXACT = 3        /* k = n_slices: the serial fine solution           */
+} rbc_stop;
 typedef enum { RBC_ARS222 = 2, RBC_ARS443 = 4 } rbc_scheme;
 
 /* Problem and discretisation.  Section 2.1 gives the equations and the
@@ -96,6 +115,11 @@ typedef struct {
                               starts as soon as its initial state is
                               corrected; results identical to 0, the
                               sweep-then-batch order).  Default 1.          */
+  double stat_tol;         /* statistics-based stop (section 5; needs
+                              nu_stride > 0 and a history pointer): after
+                              iteration k >= 1, stop when each time-averaged
+                              Nu_V, Nu_b, Nu_t changed by <= stat_tol
+                              (relative) from iteration k-1.  0 = off.      */
 } rbc_params;
 
 /* Fill p with defaults (T_bot = 1, T_top = 0, ARS443, FP64, no sampling). */
@@ -132,8 +156,8 @@ rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double noise_amp, double*
  * Eq. 13): n_steps IMEX steps of the fine grid on each of n_slices
  * independent states.  U_in and U_out are [n_slices][state] (they may be
  * the same pointer).  If nu_samples_dev is not NULL and nu_stride > 0 it
- * receives [n_slices][n_steps / nu_stride][3] = (Nu_V, Nu_b, Nu_t) after
- * every nu_stride-th step.  n_slices <= the handle's n_slices. */
+ * receives [n_slices][n_steps / nu_stride][RBC_DIAG] diagnostic records
+ * after every nu_stride-th step.  n_slices <= the handle's n_slices. */
 rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in_dev, double* U_out_dev,
                                int32_t n_slices, int32_t n_steps, double* nu_samples_dev);
 
@@ -165,16 +189,21 @@ rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first_slice,
  * F result as it completes.  The result is the same, bit for bit, as the
  * sweep-then-batch order; the work after a converged iteration is started
  * speculatively and discarded.  Stops when the defect is
- * <= tol, at k = k_max, or at k = n_slices (then U equals the serial fine
- * solution).  defect_hist_host[k-1] gets the defect of iteration k
- * (k_max entries).  nu_avg_hist_host, if not NULL and nu_stride > 0,
- * gets [k_max + 1][3]: the time average over [nu_t_start, t_end] of
- * (Nu_V, Nu_b, Nu_t) along the trajectories of iteration k (k = 0: the
- * coarse trajectory).  Returns RBC_NOT_CONVERGED if stopped by k_max with
- * the defect above tol > 0, RBC_ERR_NONFINITE on NaN/Inf. */
+ * <= tol, when the time-averaged Nusselt numbers settle (p.stat_tol), at
+ * k = k_max, or at k = n_slices (then U equals the serial fine solution);
+ * rbc_stop_reason tells which.  defect_hist_host[k-1] gets the defect of
+ * iteration k (k_max entries).  nu_avg_hist_host, if not NULL and
+ * nu_stride > 0, gets [k_max + 1][RBC_DIAG_AVG]: the time averages over
+ * [nu_t_start, t_end] of the diagnostic records sampled along the
+ * trajectories of iteration k (k = 0: the coarse trajectory).  Returns
+ * RBC_NOT_CONVERGED if stopped by k_max with the defect above tol > 0,
+ * RBC_ERR_NONFINITE on NaN/Inf. */
 rbc_status parareal_iterate(rbc_handle h, double* U_dev, int32_t k_max, double tol,
                             int32_t* k_done_host, double* defect_hist_host,
                             double* nu_avg_hist_host);
+
+/* Why the last parareal_iterate stopped (rbc_stop; -1 before any). */
+rbc_status rbc_stop_reason(rbc_handle h, int32_t* reason);
 
 /* First iteration whose fine runs the last parareal_iterate ran in FP64
  * (promote_fp64; its coarse sweeps switched one iteration earlier), 0 if it
@@ -202,6 +231,10 @@ rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out);
  * mean at z = 0 and z = Lz.  Nu_V: volume mean of -dT/dz + sqrt(Ra Pr) w T,
  * integrated exactly for the discrete fields.  Synchronises. */
 rbc_status rbc_nusselt(rbc_handle h, const double* U_dev, int32_t n_states, double* nu_host);
+
+/* The diagnostic records (RBC_DIAG doubles each, section 2.2) of n_states
+ * fine states into out_host[n_states][RBC_DIAG].  Synchronises. */
+rbc_status rbc_diagnostics(rbc_handle h, const double* U_dev, int32_t n_states, double* out_host);
 
 /* Diagnostic: the explicit (advective) terms of one fine state in the
  * equations' bases: E_dev gets a state-shaped array whose field 0 holds

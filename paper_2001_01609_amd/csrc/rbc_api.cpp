@@ -2,6 +2,7 @@
 // state, the fine propagator over a batch of slices and the diagnostics; the
 // coarse sweep and the Parareal iteration are in rbc_parareal.cpp.  Every
 // arithmetic step runs in the HIP kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -57,6 +58,7 @@ std::string check_params(const rbc_params* p) {
     if (s != RBC_ARS222 && s != RBC_ARS443) return "scheme must be RBC_ARS222 or RBC_ARS443";
   if (p->precision != RBC_FP64 && p->precision != RBC_MIXED) return "precision must be RBC_FP64 or RBC_MIXED";
   if (p->nu_stride < 0) return "nu_stride must be >= 0";
+  if (!(p->stat_tol >= 0)) return "stat_tol must be >= 0";
   return "";
 }
 
@@ -101,7 +103,7 @@ size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::Gri
   b += (S + 2) * 4 * f.Mx * f.Nz * 8 + (S + 2) * 16; // state ring, slot records
   b += S * 4 * c.Mx * c.Nz * 8;                     // G
   b += (S + 1) * rbc::kCombineBlocks * 2 * 8 + 64;  // partials, scalars
-  b += 2 * S * size_t(nsf) * 3 * 8 + S * size_t(nsc) * 3 * 8;
+  b += 2 * S * size_t(nsf) * rbc::kDiag * 8 + S * size_t(nsc) * rbc::kDiag * 8;
   return b;
 }
 
@@ -158,6 +160,7 @@ rbc_status rbc_default_params(rbc_params* p) {
   p->T_bot = 1; p->T_top = 0;
   p->promote_fp64 = 1;
   p->pipelined = 1;
+  p->stat_tol = 0;
   return RBC_OK;
 }
 
@@ -249,11 +252,11 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
       hipMalloc((void**)&h->part, (S + 1) * rbc::kCombineBlocks * 2 * 8) != hipSuccess ||
       hipMalloc((void**)&h->dscal, 64) != hipSuccess)
     return bail(RBC_ERR_OOM, "parareal buffers");
-  if (h->nsf > 0 && hipMalloc((void**)&h->nu_f, 2 * S * h->nsf * 3 * 8) != hipSuccess)
+  if (h->nsf > 0 && hipMalloc((void**)&h->nu_f, 2 * S * h->nsf * rbc::kDiag * 8) != hipSuccess)
     return bail(RBC_ERR_OOM, "nu sample buffer");
-  if (h->nsc > 0 && hipMalloc((void**)&h->nu_c, S * h->nsc * 3 * 8) != hipSuccess)
+  if (h->nsc > 0 && hipMalloc((void**)&h->nu_c, S * h->nsc * rbc::kDiag * 8) != hipSuccess)
     return bail(RBC_ERR_OOM, "nu sample buffer");
-  if (hipHostMalloc((void**)&h->host_pin, (2 + 2 * S * h->nsf * 3 + S * h->nsc * 3) * 8, hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&h->host_pin, (2 + (2 * S * h->nsf + S * h->nsc) * rbc::kDiag) * 8, hipHostMallocDefault) !=
       hipSuccess)
     return bail(RBC_ERR_OOM, "pinned host buffer");
   // the pipelined iteration's two streams (default priority)
@@ -359,18 +362,40 @@ rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in, double* U_out, 
   return RBC_OK;
 }
 
-rbc_status rbc_nusselt(rbc_handle h, const double* U, int32_t n, double* nu_host) {
-  if (!h || !U || !nu_host || n < 0) return fail(h, RBC_ERR_ARG, "bad argument");
-  if (n == 0) return RBC_OK;
+// Diagnostic records of n fine states into host memory (batches of at most
+// the work buffers' capacity).
+static rbc_status diag_states(rbc_handle h, const double* U, int n, double* host, const char* what) {
   double* d = nullptr;
-  HIPCHK(h, hipMallocAsync((void**)&d, size_t(n) * 3 * 8, h->stream));
-  hipError_t e = rbc::launch_nusselt(h->fine, U, n, d, 3, h->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(nu_host, d, size_t(n) * 3 * 8, hipMemcpyDeviceToHost, h->stream);
+  HIPCHK(h, hipMallocAsync((void**)&d, size_t(n) * rbc::kDiag * 8, h->stream));
+  hipError_t e = hipSuccess;
+  for (int i0 = 0; i0 < n && e == hipSuccess; i0 += h->wf.cap) {
+    const int cnt = std::min(h->wf.cap, n - i0);
+    e = rbc::launch_diag(h->fine, h->wf, U + size_t(i0) * h->fine.dev.state, 0, cnt, cnt, d + size_t(i0) * rbc::kDiag,
+                         rbc::kDiag, nullptr, 0, 1, 0, 0, h->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(host, d, size_t(n) * rbc::kDiag * 8, hipMemcpyDeviceToHost, h->stream);
   hipError_t e2 = hipFreeAsync(d, h->stream);
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return fail(h, RBC_ERR_HIP, std::string("rbc_nusselt: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(h, RBC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
   return RBC_OK;
+}
+
+rbc_status rbc_nusselt(rbc_handle h, const double* U, int32_t n, double* nu_host) {
+  if (!h || !U || !nu_host || n < 0) return fail(h, RBC_ERR_ARG, "bad argument");
+  if (n == 0) return RBC_OK;
+  std::vector<double> rec(size_t(n) * rbc::kDiag);
+  rbc_status s = diag_states(h, U, n, rec.data(), "rbc_nusselt");
+  if (s != RBC_OK) return s;
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) nu_host[size_t(i) * 3 + c] = rec[size_t(i) * rbc::kDiag + c];
+  return RBC_OK;
+}
+
+rbc_status rbc_diagnostics(rbc_handle h, const double* U, int32_t n, double* out_host) {
+  if (!h || !U || !out_host || n < 0) return fail(h, RBC_ERR_ARG, "bad argument");
+  if (n == 0) return RBC_OK;
+  return diag_states(h, U, n, out_host, "rbc_diagnostics");
 }
 
 rbc_status rbc_explicit_terms(rbc_handle h, const double* U, double* E) {

@@ -17,6 +17,7 @@ struct rbc_ctx {
   rbc::GridPlan fine64, coarse64;   // all-FP64 plans for promoted sweeps (mixed + promote_fp64)
   bool has64 = false;
   int k_fp64 = 0;              // first iteration the last parareal_iterate ran F in FP64 (0: never)
+  int stop_reason = -1;        // of the last parareal_iterate (rbc_stop_reason)
   rbc::Work wf, wc, wf64, wc64;  // fine work for ring_cap slices, coarse work for one
   int nf = 0, nc = 0;          // steps per slice
   int ring_cap = 0;            // fine state slots: n_slices + 2
@@ -27,9 +28,9 @@ struct rbc_ctx {
   double* Gbuf = nullptr;      // [S][cstate]  coarse part of G(U_n^k)
   double* part = nullptr;      // [S+1][kCombineBlocks][2]
   double* dscal = nullptr;     // [2] defect, non-finite flag
-  double* nu_f = nullptr;      // [2][S][nsf][3]  (sequential: first half)
-  double* nu_c = nullptr;      // [S][nsc][3]
-  double* host_pin = nullptr;  // pinned: [2] defect + [2][S][nsf][3] + [S][nsc][3]
+  double* nu_f = nullptr;      // [2][S][nsf][kDiag]  diagnostic samples (sequential: first half)
+  double* nu_c = nullptr;      // [S][nsc][kDiag]
+  double* host_pin = nullptr;  // pinned: [2] defect + [2][S][nsf][kDiag] + [S][nsc][kDiag]
   int nsf = 0, nsc = 0, stride_c = 0;
   std::vector<hipEvent_t> evpool;  // events of the pipelined iteration, reused across calls
   // graphs of kCoarseGraphSteps coarse steps on Xc (mixed / FP64 coarse plan),

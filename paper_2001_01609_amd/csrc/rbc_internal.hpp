@@ -23,6 +23,10 @@
 namespace rbc {
 
 constexpr int kMaxStages = 5;     // s + 1 stages of ARS(4,4,3)
+constexpr int kDiag = 6;          // diagnostic record: Nu_V, Nu_b, Nu_t, KE, epsilon_U, P
+constexpr int kDiagAvg = 9;       // time averages: Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, epsilon_U, P, |P-eps|/P
+// Fourier modes per block of the diagnostics kernel (Nz coefficients each).
+__host__ __device__ inline int diag_modes(int Nz) { return Nz >= 512 ? 1 : 512 / Nz; }
 constexpr int kBlock = 256;       // threads per block of the per-mode kernels
 
 // Per-row entries of the stored bordered band factorisations (rbc_plan.cpp).
@@ -94,6 +98,7 @@ struct Work {
   void* qbar = nullptr;    // Real [cap][Pz]
   void* Ehist = nullptr;   // Real [s][cap][state]
   double* LYhist = nullptr;  // [s-1][cap][state]
+  double* dpart = nullptr;   // [cap][mode chunks][4] diagnostic partial sums
 };
 size_t work_bytes(const GridPlan& g, int cap);
 hipError_t alloc_work(const GridPlan& g, int cap, Work& w);
@@ -113,8 +118,8 @@ struct KernelTiming {
 
 // ---- launchers (rbc_kernels.hip) -----------------------------------------
 // Advance n_slices contiguous states X in place by n_steps IMEX steps.  If
-// nu_out is not null, after every nu_stride-th step the Nusselt numbers of each
-// slice go to nu_out[s * nu_ld + sample][3].
+// nu_out is not null, after every nu_stride-th step the diagnostic record of
+// each slice goes to nu_out[(s * nu_ld + sample) * kDiag ..].
 hipError_t launch_steps(const GridPlan& g, Work& w, double* X, int n_slices, int n_steps,
                         double* nu_out, int nu_stride, int nu_ld, hipStream_t st,
                         KernelTiming* timing = nullptr);
@@ -134,24 +139,22 @@ struct StepRange {
 hipError_t launch_step_range(const GridPlan& g, Work& w, double* X, const StepRange& r, double* nu_out,
                              int nu_stride, int nu_ld, hipStream_t st, KernelTiming* timing = nullptr);
 
-// Per-slot record of the pipelined Parareal's fine runs: the run's Nu
-// samples go to buffer `par` (iteration parity), slice n; it started at
-// virtual fine step `start`.
+// Per-slot record of the pipelined Parareal's fine runs: the run's
+// diagnostic samples go to buffer `par` (iteration parity), slice n; it
+// started at virtual fine step `start`.
 struct SlotMeta {
   int par, n, start, pad;
 };
 hipError_t launch_set_meta(SlotMeta* meta, int slot, SlotMeta v, hipStream_t st);
-// Nusselt numbers after virtual fine step t of the runs in ring slots
-// slot0.. (count of them, mod cap) of X: a run that has completed a
-// multiple q+1 of `stride` own steps writes nu[(par * S + n) * nsf + q][3].
-hipError_t launch_nusselt_ring(const GridPlan& g, const double* X, int slot0, int count, int cap,
-                               const SlotMeta* meta, int t, int stride, int nsf, int S, double* nu,
-                               hipStream_t st);
+// Diagnostic records (kDiag values) of `count` states at batch positions
+// slot0, slot0 + 1, ... (mod cap) of X; count <= w.cap (partial sums in
+// w.dpart).  Without meta, state i writes out[i * ld .. + kDiag]; with meta
+// (the pipelined ring, at virtual fine step t) a run that has completed a
+// multiple q+1 of `stride` own steps writes out[((par S + n) nsf + q) kDiag].
+hipError_t launch_diag(const GridPlan& g, Work& w, const double* X, int slot0, int count, int cap, double* out,
+                       int ld, const SlotMeta* meta, int t, int stride, int nsf, int S, hipStream_t st);
 // Explicit terms of one state (diagnostic): E = state-shaped FP64 array.
 hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st);
-// Nusselt numbers of n states: out[i*ld3 .. +3] (ld3 = stride in doubles).
-hipError_t launch_nusselt(const GridPlan& g, const double* X, int n, double* out, int ld3,
-                          hipStream_t st);
 // Fine -> coarse restriction (truncation).
 hipError_t launch_restrict(const GridPlan& f, const GridPlan& c, const double* Xf, double* Xc,
                            hipStream_t st);

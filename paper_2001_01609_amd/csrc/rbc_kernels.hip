@@ -528,6 +528,37 @@ __device__ __forceinline__ RowTables load_row_tables(const GridDev& g, int r) {
   return t;
 }
 
+// Byte offsets of the stage kernel's LDS regions beyond the two FP64 tiles
+// and the product region: the staged factor blocks of the temperature (sFT)
+// and streamfunction (sFP) equations.  Without `pre` both take turns in the
+// union with the products; with `pre` each has its own region, filled at
+// kernel entry.  Phase G's scratch starts at the old-state tile.
+struct StageLds {
+  size_t sFT, sFP, total;
+};
+template <int NZ, int MT>
+__host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool pre) {
+  constexpr size_t PZ = 3 * NZ / 2;
+  const size_t tile = sizeof(double) * 4 * MT * (NZ + 1);
+  const size_t nh = rb * (4 * PZ * MT + PZ);
+  const size_t vals = rb * PZ * MT * 12;
+  StageLds L{};
+  if (!pre) {
+    const size_t fac = sizeof(double) * size_t(MT) * 2 * size_t((fsT > fsP ? fsT : fsP) | 1);
+    const size_t uni = nh > fac ? nh : fac;
+    L.sFT = L.sFP = 2 * tile;
+    L.total = tile + (tile + uni > vals ? tile + uni : vals);
+    return L;
+  }
+  size_t o = 2 * tile + ((nh + 15) & ~size_t(15));
+  L.sFT = o;
+  o += sizeof(double) * size_t(MT) * 2 * size_t(fsT | 1);
+  L.sFP = o;
+  o += sizeof(double) * size_t(MT) * 2 * size_t(fsP | 1);
+  L.total = o > tile + vals ? o : tile + vals;
+  return L;
+}
+
 // One block per (slice, tile of MT modes).  Each thread owns one row
 // r = tid mod NZ of the equations and the columns c = tid / NZ + k (256/NZ)
 // of the tile (column c = (field, mode, re/im)).
@@ -536,6 +567,8 @@ __device__ __forceinline__ RowTables load_row_tables(const GridDev& g, int r) {
 //   sY  [2 field][MT][2][NZ+1]   right-hand sides -> new stage values
 //   sX  [2 field][MT][2][NZ+1]   old state of the tile
 //   U   union { Real sN[2][PZ][2 MT] + sq[PZ];  double sF[2 MT][odd stride] }
+//   (latency variant: sN + sq, then the factor blocks of both equations in
+//   regions of their own; see stage_lds)
 template <typename Real, int NZ, int MT>
 __global__ void __launch_bounds__(kBlock)
 stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __restrict__ qbar,
@@ -550,6 +583,13 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   // sweep, the largest Nz): more work items per phase and register-held
   // solves.  Wider tiles serve the throughput-bound batched launches.
   constexpr bool kWide = (MT <= 2);
+  // Latency variant of the small two-mode launches: the loads that do not
+  // depend on this launch's own results (factor blocks, band rows, stage
+  // history) are issued at entry beside the product loads instead of at the
+  // start of the phases that use them.  (The transform maps stay in global
+  // memory: staged in LDS they cost more at entry and in bank conflicts than
+  // their cached loads.)
+  constexpr bool kPre = kWide && NZ <= 64;
   static_assert(kBlock % NZ == 0, "NZ must divide the block size");
   extern __shared__ __align__(16) unsigned char smem[];
   const int Mx = g.Mx;
@@ -563,7 +603,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   unsigned char* uni = reinterpret_cast<unsigned char*>(sX + 4 * MT * LD);
   Real* sN = reinterpret_cast<Real*>(uni);
   Real* sq = sN + 4 * PZ * MT;
-  double* sF = reinterpret_cast<double*>(uni);
+  const StageLds Ls = stage_lds<NZ, MT>(sizeof(Real), g.facT_stride, g.facP_stride, kPre);
+  double* sFT = reinterpret_cast<double*>(smem + Ls.sFT);
+  double* sFP = reinterpret_cast<double*>(smem + Ls.sFP);
   const int tid = threadIdx.x;
   const int r = tid % NZ, c0 = tid / NZ;     // this thread's row and first column
   // column c -> (field, mode within tile, re/im); LDS and HBM offsets
@@ -575,12 +617,80 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   };
   const double* Xs = X + size_t(s) * st;
 
+  // ---- kPre: entry loads into registers (stored to LDS by pre_store)
+  constexpr int FTN = (MT * 2 * 2 * NZ + kBlock - 1) / kBlock;        // facT stride 2 Nz
+  constexpr int FPN = (MT * 2 * (7 * NZ / 2) + kBlock - 1) / kBlock;  // facP stride <= 3.5 Nz
+  double fT[kPre ? FTN : 1], fP[kPre ? FPN : 1];
+  double hE[kPre ? KC : 1][3], hL[kPre ? KC : 1][3];
+  RowTables tbp{};
+  const bool stg = (a.mode == kModeStage);
+  const int nmt = min(MT, Mx - m0);
+  const int totT = stg ? nmt * 2 * g.facT_stride : 0, totP = stg ? nmt * 2 * g.facP_stride : 0;
+  if constexpr (kPre) {
+    const double* srcT = g.facT + size_t(m0) * 2 * g.facT_stride;
+    const double* srcP = g.facP + size_t(m0) * 2 * g.facP_stride;
+#pragma unroll
+    for (int u = 0; u < FTN; ++u) {
+      const int e = tid + u * kBlock;
+      fT[u] = (e < totT) ? srcT[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < FPN; ++u) {
+      const int e = tid + u * kBlock;
+      fP[u] = (e < totP) ? srcP[e] : 0.0;
+    }
+    if (stg) tbp = load_row_tables(g, r);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const int c = c0 + kc * CR;
+      const bool ok = stg && c < NC && m0 + mtc(c) < Mx &&
+                      r < ((fld(c) == 0 && m0 + mtc(c) > 0) ? NZ - 4 : NZ - 2);
+      const size_t off = ok ? goff(c) + r : 0;
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        hE[kc][jj] = (ok && jj + 1 < a.stage) ? double(Ehist[(size_t(jj) * a.cap + s) * st + off]) : 0.0;
+        hL[kc][jj] = (ok && jj + 2 <= a.stage) ? LYhist[(size_t(jj) * a.cap + s) * st + off] : 0.0;
+      }
+    }
+  }
+  auto pre_store = [&]() {
+    if constexpr (kPre) {
+      const int lsT = lds_fac_stride(g.facT_stride), lsP = lds_fac_stride(g.facP_stride);
+#pragma unroll
+      for (int u = 0; u < FTN; ++u) {
+        const int e = tid + u * kBlock;
+        if (e < totT) {
+          const int bb = e / g.facT_stride;
+          sFT[bb * lsT + (e - bb * g.facT_stride)] = fT[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FPN; ++u) {
+        const int e = tid + u * kBlock;
+        if (e < totP) {
+          const int bb = e / g.facP_stride;
+          sFP[bb * lsP + (e - bb * g.facP_stride)] = fP[u];
+        }
+      }
+      // factor blocks longer than the register bound (not for the plans built here)
+      for (int e = FTN * kBlock + tid; e < totT; e += kBlock) {
+        const int bb = e / g.facT_stride;
+        sFT[bb * lsT + (e - bb * g.facT_stride)] = g.facT[size_t(m0) * 2 * g.facT_stride + e];
+      }
+      for (int e = FPN * kBlock + tid; e < totP; e += kBlock) {
+        const int bb = e / g.facP_stride;
+        sFP[bb * lsP + (e - bb * g.facP_stride)] = g.facP[size_t(m0) * 2 * g.facP_stride + e];
+      }
+    }
+  };
+
   if (a.mode == kModeZinv) {
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       const int c = c0 + kc * CR;
       if (c < NC) sY[yoff(c) + r] = (m0 + mtc(c) < Mx) ? Xs[goff(c) + r] : 0.0;
     }
+    pre_store();
     __syncthreads();
   } else {
     // ---- phase A: products of this tile on the padded Gauss points (two
@@ -615,6 +725,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (c < NC) sX[yoff(c) + r] = (m0 + mtc(c) < Mx) ? Xs[goff(c) + r] : 0.0;
       }
     }
+    pre_store();
     __syncthreads();
     const Real* W = reinterpret_cast<const Real*>(g.Wfwd);
     // writes the explicit terms of item (f, row) to LDS (scaled) and HBM
@@ -726,9 +837,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     if (a.mode == kModeExplicit) return;
     __syncthreads();
     // temperature factors into the (now free) union region
-    stage_factors<MT>(sF, g.facT, g.facT_stride, m0, Mx);
+    if constexpr (!kPre) stage_factors<MT>(sFT, g.facT, g.facT_stride, m0, Mx);
     // ---- phase C: right-hand side of stage i on this thread's row
-    const RowTables tb = load_row_tables(g, r);
+    const RowTables tb = kPre ? tbp : load_row_tables(g, r);
     {
       double acc[KC];
 #pragma unroll
@@ -757,10 +868,19 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         }
         const size_t off = goff(c) + r;
         double h = MX + sY[yoff(c) + r];
-        for (int jj = 0; jj + 1 < a.stage; ++jj)
-          h += a.hae[jj] * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
-        for (int jj = 1; jj < a.stage; ++jj)
-          h += a.hai[jj] * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
+        if constexpr (kPre) {
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj)
+            if (jj + 1 < a.stage) h += a.hae[jj] * hE[kc][jj];
+#pragma unroll
+          for (int jj = 1; jj < 4; ++jj)
+            if (jj < a.stage) h += a.hai[jj] * hL[kc][jj - 1];
+        } else {
+          for (int jj = 0; jj + 1 < a.stage; ++jj)
+            h += a.hae[jj] * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
+          for (int jj = 1; jj < a.stage; ++jj)
+            h += a.hai[jj] * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
+        }
         acc[kc] = h;
       }
 #pragma unroll
@@ -785,7 +905,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
             double gbc = 0.0;
             if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
             solve_T_scan<NRT, WS>(sY + ((MT + mt) * 2 + ri) * LD, p,
-                                  sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc, li);
+                                  sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc, li);
           }
         }
       }
@@ -795,12 +915,12 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         double gbc = 0.0;
         if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
         solve_T_format<NRT, kWide>(sY + ((MT + mt) * 2 + ri) * LD, p,
-                                   sF + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc);
+                                   sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc);
       }
     }
     __syncthreads();
     // flow factors; implicit buoyancy of the new temperature into psi
-    stage_factors<MT>(sF, g.facP, g.facP_stride, m0, Mx);
+    if constexpr (!kPre) stage_factors<MT>(sFP, g.facP, g.facP_stride, m0, Mx);
     if (r < NZ - 4) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
@@ -825,7 +945,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (sys < 4 * MT) {
           const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
           if (m < Mx) {
-            const double* fac = sF + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
+            const double* fac = sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
             double* v = sY + (mt * 2 + ri) * LD;
             if (m == 0)
               solve_T_scan<NRT, WS>(v, p, fac, 0.0, li);
@@ -837,7 +957,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     } else if (tid < 4 * MT) {
       const int mt = tid >> 2, p = (tid >> 1) & 1, ri = tid & 1, m = m0 + mt;
       if (m < Mx) {
-        const double* fac = sF + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
+        const double* fac = sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
         double* v = sY + (mt * 2 + ri) * LD;
         if (m == 0)
           solve_T_format<NRT, kWide>(v, p, fac, 0.0);
@@ -1056,70 +1176,156 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   }
 }
 
-// ------------------------------------------------------------------ Nusselt ---
+// ------------------------------------------------------------- diagnostics ---
+//
+// The per-state record of section 2.2 (Nu_V, Nu_b, Nu_t, KE, epsilon_U, P)
+// from exact volume means of products of the discrete fields.  For real
+// fields f, g with modes f_m, g_m (m >= 0), the horizontal mean of f g is
+// f_0 g_0 + 2 sum_{m>=1} Re(f_m conj g_m); the vertical mean over z in
+// [0, Lz] of two Chebyshev series a, b is (1/2) sum_ab a_a b_b J_ab with
+// J_ab = int_{-1}^{1} T_a T_b = 1/(1-(a+b)^2) + 1/(1-(a-b)^2) for a + b even
+// (zero otherwise).  u = psi_z (u_bar for m = 0), w = -i k psi,
+// omega = psi_zz - k^2 psi (u_bar_z for m = 0); <|grad u|^2> = <omega^2> for
+// these no-slip, periodic fields.  Two kernels: partial sums per (state,
+// chunk of modes), then a fixed-order sum per state.
 
-// One block per state.  <w T> = sum_{m>=1} Re(w_m^T J conj(T_m)) with
-// J_ab = int_{-1}^{1} T_a T_b = (I(a+b) + I(|a-b|))/2, I(n) = 2/(1-n^2) for
-// even n; w_m = -i k psi_m.  Fixed-order partial sums and tree reduction.
-__device__ void nusselt_block(const GridDev& g, const double* __restrict__ x, double* __restrict__ o,
-                              double* red) {
-  const int Nz = g.Nz, Mx = g.Mx;
-  double acc = 0;
-  for (int e = threadIdx.x; e < (Mx - 1) * Nz; e += blockDim.x) {
-    const int m = 1 + e / Nz, aa = e % Nz;
-    const double k = m * g.kscale;
-    const double pr = x[((0 * Mx + m) * 2 + 0) * Nz + aa], pim = x[((0 * Mx + m) * 2 + 1) * Nz + aa];
-    const double wr = k * pim, wi = -k * pr;
-    const double* tr = x + size_t((1 * Mx + m) * 2 + 0) * Nz;
-    const double* ti = x + size_t((1 * Mx + m) * 2 + 1) * Nz;
-    double sr = 0, si = 0;
-    for (int b = aa & 1; b < Nz; b += 2) {
-      const int sp = aa + b, df = aa > b ? aa - b : b - aa;
-      const double J = 1.0 / (1.0 - double(sp) * sp) + 1.0 / (1.0 - double(df) * df);
-      sr += J * tr[b];
-      si += J * ti[b];
-    }
-    acc += wr * sr + wi * si;
+// Chebyshev-T coefficients of d/dzeta of c[0..N) into d[0..N):
+// d_n = d_(n+2) + 2 (n+1) c_(n+1), then d_0 / 2.
+__device__ void cheb_deriv_col(const double* c, double* d, int N, double scale) {
+  double a = 0.0, b = 0.0;   // d_(n+1), d_(n+2)
+  d[N - 1] = 0.0;
+  for (int n = N - 2; n >= 0; --n) {
+    const double v = b + 2.0 * (n + 1) * c[n + 1];
+    d[n] = v;
+    b = a;
+    a = v;
   }
-  red[threadIdx.x] = acc;
+  d[0] *= 0.5;
+  for (int n = 0; n < N; ++n) d[n] *= scale;
+}
+
+// Block-wide sum of four values; thread 0 receives the totals.
+__device__ void block_sum4(double v[4], double* red) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[wv * 4 + q] = v[q];
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double* tm = x + size_t((1 * Mx + 0) * 2 + 0) * Nz;
-    double nb = 0, nt = 0, t0 = 0, t1 = 0;
-    for (int n = 0; n < Nz; ++n) {
-      const double sgn = (n & 1) ? -1.0 : 1.0, n2 = double(n) * n;
-      nb += tm[n] * (-sgn) * n2;   // T_n'(-1) = (-1)^(n+1) n^2
-      nt += tm[n] * n2;            // T_n'(1) = n^2
-      t0 += tm[n] * sgn;
-      t1 += tm[n];
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[w * 4 + q];
+      v[q] = t;
     }
-    o[0] = (t0 - t1) / g.Lz + g.sqrtRaPr * red[0];
-    o[1] = -g.scale * nb;
-    o[2] = -g.scale * nt;
+}
+
+// Partial sums (<w T>, <u^2>, <w^2>, <omega^2>) of modes [chunk * MC, ...)
+// of the state at batch position blockIdx.x / nchunk.
+__global__ void __launch_bounds__(kBlock)
+diag_partial_kernel(GridDev g, const double* __restrict__ X, int slot0, int cap, int nchunk,
+                    double* __restrict__ part) {
+  extern __shared__ double sd[];
+  __shared__ double red[(kBlock / 64) * 4];
+  const int Nz = g.Nz, Mx = g.Mx, MC = diag_modes(Nz);
+  const int bpos = blockIdx.x / nchunk, chunk = blockIdx.x - bpos * nchunk;
+  const double* x = X + size_t(ring_slot(bpos, slot0, cap)) * g.state;
+  const int m0 = chunk * MC, nm = min(MC, Mx - m0);
+  double* sP = sd;                      // [MC][re, im][Nz] psi (u_bar at m = 0)
+  double* sT = sP + MC * 2 * Nz;        // T
+  double* sU = sT + MC * 2 * Nz;        // u
+  double* sO = sU + MC * 2 * Nz;        // omega
+  for (int e = threadIdx.x; e < nm * 2 * Nz; e += blockDim.x) {
+    const int mm = e / (2 * Nz), rest = e - mm * 2 * Nz;
+    sP[e] = x[size_t(0 * Mx + m0 + mm) * 2 * Nz + rest];
+    sT[e] = x[size_t(1 * Mx + m0 + mm) * 2 * Nz + rest];
   }
+  __syncthreads();
+  for (int col = threadIdx.x; col < nm * 2; col += blockDim.x) {
+    const int m = m0 + (col >> 1);
+    const double* c = sP + col * Nz;
+    double* u = sU + col * Nz;
+    double* om = sO + col * Nz;
+    if (m == 0) {
+      for (int n = 0; n < Nz; ++n) u[n] = c[n];
+      cheb_deriv_col(c, om, Nz, g.scale);
+    } else {
+      const double k = m * g.kscale;
+      cheb_deriv_col(c, u, Nz, g.scale);
+      cheb_deriv_col(u, om, Nz, g.scale);
+      for (int n = 0; n < Nz; ++n) om[n] -= k * k * c[n];
+    }
+  }
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = threadIdx.x; e < nm * Nz; e += blockDim.x) {
+    const int mm = e / Nz, a = e - mm * Nz, m = m0 + mm;
+    const double k = m * g.kscale, wgt = (m == 0) ? 0.5 : 1.0;
+    const double* pr = sP + mm * 2 * Nz; const double* pi = pr + Nz;
+    const double* tr = sT + mm * 2 * Nz; const double* ti = tr + Nz;
+    const double* ur = sU + mm * 2 * Nz; const double* ui = ur + Nz;
+    const double* orr = sO + mm * 2 * Nz; const double* oi = orr + Nz;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = a & 1; b < Nz; b += 2) {
+      const int sp = a + b, df = a > b ? a - b : b - a;
+      const double J = 1.0 / (1.0 - double(sp) * sp) + 1.0 / (1.0 - double(df) * df);
+      s[0] += J * tr[b]; s[1] += J * ti[b];
+      s[2] += J * ur[b]; s[3] += J * ui[b];
+      s[4] += J * pr[b]; s[5] += J * pi[b];
+      s[6] += J * orr[b]; s[7] += J * oi[b];
+    }
+    if (m > 0) {
+      acc[0] += wgt * k * (pi[a] * s[0] - pr[a] * s[1]);            // w = -i k psi against T
+      acc[2] += wgt * k * k * (pr[a] * s[4] + pi[a] * s[5]);        // |w|^2
+    }
+    acc[1] += wgt * (ur[a] * s[2] + ui[a] * s[3]);                  // |u|^2
+    acc[3] += wgt * (orr[a] * s[6] + oi[a] * s[7]);                 // omega^2
+  }
+  block_sum4(acc, red);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) part[size_t(blockIdx.x) * 4 + q] = acc[q];
 }
 
-__global__ void __launch_bounds__(kBlock)
-nusselt_kernel(GridDev g, const double* __restrict__ X, double* __restrict__ out, int ld3) {
-  __shared__ double red[kBlock];
-  nusselt_block(g, X + size_t(blockIdx.x) * g.state, out + size_t(blockIdx.x) * ld3, red);
-}
-
-// Ring form for the pipelined fine runs (block-uniform early exit).
-__global__ void __launch_bounds__(kBlock)
-nusselt_ring_kernel(GridDev g, const double* __restrict__ X, int slot0, int cap, const SlotMeta* __restrict__ meta,
-                    int t, int stride, int nsf, int S, double* __restrict__ nu) {
-  __shared__ double red[kBlock];
-  const int slot = ring_slot(blockIdx.x, slot0, cap);
-  const SlotMeta m = meta[slot];
-  const int d = t - m.start;
-  if (d <= 0 || d % stride != 0 || d / stride > nsf) return;
-  const int q = d / stride - 1;
-  nusselt_block(g, X + size_t(slot) * g.state, nu + ((size_t(m.par) * S + m.n) * nsf + q) * 3, red);
+// Per state: the chunk partials in order, the wall gradients of the mean
+// temperature, and the record.  Plain batches write out + bpos * ld; with
+// meta (the pipelined ring) a run that has completed a multiple q+1 of
+// `stride` own steps at virtual step t writes out[(par S + n) nsf + q][6].
+__global__ void diag_final_kernel(GridDev g, const double* __restrict__ X, int slot0, int cap, int nchunk,
+                                  const double* __restrict__ part, double* __restrict__ out, int ld,
+                                  const SlotMeta* __restrict__ meta, int t, int stride, int nsf, int S) {
+  if (threadIdx.x != 0) return;
+  const int bpos = blockIdx.x, slot = ring_slot(bpos, slot0, cap);
+  double* o;
+  if (meta) {
+    const SlotMeta mt = meta[slot];
+    const int d = t - mt.start;
+    if (d <= 0 || d % stride != 0 || d / stride > nsf) return;
+    o = out + ((size_t(mt.par) * S + mt.n) * nsf + (d / stride - 1)) * kDiag;
+  } else {
+    o = out + size_t(bpos) * ld;
+  }
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < nchunk; ++c)
+    for (int q = 0; q < 4; ++q) v[q] += part[(size_t(bpos) * nchunk + c) * 4 + q];
+  const int Nz = g.Nz;
+  const double* tm = X + size_t(slot) * g.state + size_t(1 * g.Mx + 0) * 2 * Nz;
+  double nb = 0, nt = 0, t0 = 0, t1 = 0;
+  for (int n = 0; n < Nz; ++n) {
+    const double sgn = (n & 1) ? -1.0 : 1.0, n2 = double(n) * n;
+    nb += tm[n] * (-sgn) * n2;   // T_n'(-1) = (-1)^(n+1) n^2
+    nt += tm[n] * n2;            // T_n'(1) = n^2
+    t0 += tm[n] * sgn;
+    t1 += tm[n];
+  }
+  o[0] = (t0 - t1) / g.Lz + g.sqrtRaPr * v[0];   // Nu_V
+  o[1] = -g.scale * nb;                          // Nu_b
+  o[2] = -g.scale * nt;                          // Nu_t
+  o[3] = 0.5 * (v[1] + v[2]);                    // KE
+  o[4] = g.nu * v[3];                            // epsilon_U
+  o[5] = v[0];                                   // P = <w T>
 }
 
 __global__ void set_meta_kernel(SlotMeta* meta, int slot, SlotMeta v) {
@@ -1204,24 +1410,13 @@ __global__ void defect_kernel(const double* __restrict__ part, int first, int la
 
 namespace {
 
-template <int NZ, int MT>
-constexpr size_t stage_lds_t(size_t rb, int fac_stride) {
-  constexpr size_t PZ = 3 * NZ / 2;
-  const size_t tile = sizeof(double) * 4 * MT * (NZ + 1);
-  const size_t nh = rb * (4 * PZ * MT + PZ);
-  const size_t fac = sizeof(double) * size_t(MT) * 2 * (fac_stride | 1);
-  const size_t uni = nh > fac ? nh : fac;
-  const size_t vals = rb * PZ * MT * 12;
-  return tile + (tile + uni > vals ? tile + uni : vals);
-}
-
 template <typename Real, int NZ, int MT>
 hipError_t run_stage_t(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
                        hipStream_t st) {
   const GridDev& d = g.dev;
   const int ntile = (d.Mx + MT - 1) / MT;
-  const int fs = d.facT_stride > d.facP_stride ? d.facT_stride : d.facP_stride;
-  const size_t lds = stage_lds_t<NZ, MT>(sizeof(Real), fs);
+  constexpr bool pre = MT <= 2 && NZ <= 64;   // as in the kernel
+  const size_t lds = stage_lds<NZ, MT>(sizeof(Real), d.facT_stride, d.facP_stride, pre).total;
   hipLaunchKernelGGL((stage_kernel<Real, NZ, MT>), dim3(n_slices * ntile), dim3(kBlock), lds, st, d, a,
                      (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q, Eout);
   return hipGetLastError();
@@ -1349,11 +1544,10 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, const StepRange& r,
     }
     if (nu_out && nu_stride > 0 && (step + 1) % nu_stride == 0) {
       const int sample = (step + 1) / nu_stride - 1;
-      if (sample < nu_ld) {
-        hipLaunchKernelGGL(nusselt_kernel, dim3(r.count), dim3(kBlock), 0, st, g.dev, X, nu_out + size_t(sample) * 3,
-                           nu_ld * 3);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-      }
+      if (sample < nu_ld &&
+          (e = launch_diag(g, w, X, 0, r.count, w.cap, nu_out + size_t(sample) * kDiag, nu_ld * kDiag, nullptr, 0,
+                           1, 0, 0, st)) != hipSuccess)
+        return e;
     }
   }
   return hipSuccess;
@@ -1407,16 +1601,17 @@ hipError_t launch_set_meta(SlotMeta* meta, int slot, SlotMeta v, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_nusselt_ring(const GridPlan& g, const double* X, int slot0, int count, int cap,
-                               const SlotMeta* meta, int t, int stride, int nsf, int S, double* nu, hipStream_t st) {
-  if (count < 1 || count > cap || slot0 < 0 || slot0 >= cap || stride < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(nusselt_ring_kernel, dim3(count), dim3(kBlock), 0, st, g.dev, X, slot0, cap, meta, t, stride,
-                     nsf, S, nu);
-  return hipGetLastError();
-}
-
-hipError_t launch_nusselt(const GridPlan& g, const double* X, int n, double* out, int ld3, hipStream_t st) {
-  hipLaunchKernelGGL(nusselt_kernel, dim3(n), dim3(kBlock), 0, st, g.dev, X, out, ld3);
+hipError_t launch_diag(const GridPlan& g, Work& w, const double* X, int slot0, int count, int cap, double* out,
+                       int ld, const SlotMeta* meta, int t, int stride, int nsf, int S, hipStream_t st) {
+  if (count < 1 || count > w.cap || slot0 < 0 || slot0 >= cap || (meta && stride < 1)) return hipErrorInvalidValue;
+  const int MC = diag_modes(g.dev.Nz), nchunk = (g.dev.Mx + MC - 1) / MC;
+  const size_t lds = sizeof(double) * 8 * size_t(MC) * g.dev.Nz;
+  hipLaunchKernelGGL(diag_partial_kernel, dim3(count * nchunk), dim3(kBlock), lds, st, g.dev, X, slot0, cap, nchunk,
+                     w.dpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(count), dim3(64), 0, st, g.dev, X, slot0, cap, nchunk,
+                     (const double*)w.dpart, out, ld, meta, t, stride, nsf, S);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ rbc_status sweep(rbc_handle h, int mode, int first, double* U, const double* F, 
   rbc::Work& cw = use64 ? h->wc64 : h->wc;
   for (int n = first; n < S; ++n) {
     RBC_HIPCHK(h, rbc::launch_restrict(h->fine, cp, U + n * fs, h->Xc, h->stream));
-    double* nu = (with_nu && h->nu_c) ? h->nu_c + size_t(n) * h->nsc * 3 : nullptr;
+    double* nu = (with_nu && h->nu_c) ? h->nu_c + size_t(n) * h->nsc * rbc::kDiag : nullptr;
     RBC_HIPCHK(h, rbc::launch_steps(cp, cw, h->Xc, 1, h->nc, nu, h->stride_c, h->nsc, h->stream));
     RBC_HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, mode, U + (n + 1) * fs, mode == 1 ? F + n * fs : nullptr,
                                       h->Xc, G + n * cs, h->part + size_t(n + 1) * rbc::kCombineBlocks * 2,
@@ -77,33 +77,62 @@ rbc_status read_defect(rbc_handle h, int first, int last, double* defect, bool* 
   return RBC_OK;
 }
 
-// Time average over [nu_t_start, t_end] of the Nu samples of slices [0, S);
-// slice(n) points at slice n's [ns][3] samples.  Fixed summation order.
+// Time averages over [nu_t_start, t_end] of the diagnostic samples of slices
+// [0, S) (slice(n) points at slice n's [ns][kDiag] records), the consistency
+// checks of section 2.2: out = (Nu_V, Nu_b, Nu_t, Nu_int (Eq. 11), KE, Re,
+// epsilon_U, P, |P - epsilon_U| / P (Eq. 12)); Re is the mean RMS velocity
+// <u^2 + w^2>^(1/2) = (2 KE)^(1/2) over the viscosity.  Fixed summation
+// order.
 template <typename SliceFn>
-void nu_average_host(rbc_handle h, int ns, int stride, double dt, SliceFn slice, double* out3) {
+void diag_average_host(rbc_handle h, int ns, int stride, double dt, double nu, SliceFn slice, double* out) {
   const int S = h->p.n_slices;
   const double dT = (h->p.t_end - h->p.t0) / S;
-  double acc[3] = {0, 0, 0};
+  double acc[rbc::kDiag] = {0, 0, 0, 0, 0, 0}, urms = 0;
   long cnt = 0;
   for (int n = 0; n < S; ++n) {
     const double* b = slice(n);
     for (int q = 0; q < ns; ++q) {
       const double t = h->p.t0 + n * dT + (q + 1) * stride * dt;
       if (t < h->p.nu_t_start) continue;
-      for (int c = 0; c < 3; ++c) acc[c] += b[size_t(q) * 3 + c];
+      const double* r = b + size_t(q) * rbc::kDiag;
+      for (int c = 0; c < rbc::kDiag; ++c) acc[c] += r[c];
+      urms += std::sqrt(2.0 * r[3]);
       ++cnt;
     }
   }
-  for (int c = 0; c < 3; ++c) out3[c] = cnt ? acc[c] / cnt : NAN;
+  if (!cnt) {
+    for (int c = 0; c < rbc::kDiagAvg; ++c) out[c] = NAN;
+    return;
+  }
+  const double nv = acc[0] / cnt, nb = acc[1] / cnt, nt = acc[2] / cnt;
+  const double P = acc[5] / cnt, eps = acc[4] / cnt;
+  out[0] = nv;
+  out[1] = nb;
+  out[2] = nt;
+  out[3] = std::max(std::max(std::fabs(nb - nv), std::fabs(nb - nt)), std::fabs(nv - nt)) / nv;
+  out[4] = acc[3] / cnt;
+  out[5] = urms / cnt / nu;
+  out[6] = eps;
+  out[7] = P;
+  out[8] = std::fabs(P - eps) / P;
 }
 
-rbc_status nu_average(rbc_handle h, const double* dev, int ns, int stride, double dt, double* out3) {
+rbc_status diag_average(rbc_handle h, const double* dev, int ns, int stride, double dt, double nu, double* out) {
   const int S = h->p.n_slices;
-  std::vector<double> buf(size_t(S) * ns * 3);
+  std::vector<double> buf(size_t(S) * ns * rbc::kDiag);
   RBC_HIPCHK(h, hipMemcpyAsync(buf.data(), dev, buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
   RBC_HIPCHK(h, hipStreamSynchronize(h->stream));
-  nu_average_host(h, ns, stride, dt, [&](int n) { return buf.data() + size_t(n) * ns * 3; }, out3);
+  diag_average_host(h, ns, stride, dt, nu, [&](int n) { return buf.data() + size_t(n) * ns * rbc::kDiag; }, out);
   return RBC_OK;
+}
+
+// Statistics-based stop (section 5): the time-averaged Nusselt numbers of
+// iteration k moved by at most stat_tol (relative) from those of k - 1.
+bool stats_converged(rbc_handle h, const double* cur, const double* prev) {
+  if (!(h->p.stat_tol > 0)) return false;
+  for (int c = 0; c < 3; ++c)
+    if (!(std::fabs(cur[c] - prev[c]) <= h->p.stat_tol * std::fabs(cur[c]))) return false;
+  return true;
 }
 
 // The precision switch of promote_fp64, decided after iteration k (defect
@@ -125,18 +154,20 @@ rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, i
   if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
   if (want_nu) {
     if (h->nsc > 0) {
-      if ((s = nu_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, nu_hist)) != RBC_OK) return s;
+      if ((s = diag_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, h->coarse.dev.nu, nu_hist)) != RBC_OK)
+        return s;
     } else {
-      nu_hist[0] = nu_hist[1] = nu_hist[2] = NAN;
+      for (int c = 0; c < rbc::kDiagAvg; ++c) nu_hist[c] = NAN;
     }
   }
+  h->stop_reason = RBC_STOP_KMAX;
   double defect = INFINITY, prev = INFINITY;
   int k = 0, kG64 = INT_MAX, kF64 = INT_MAX;
   while (k < k_max && k < S) {
     ++k;
     // F on slices k-1..S-1 from U^(k-1)
     const int na = S - (k - 1);
-    double* nu = want_nu ? h->nu_f + size_t(k - 1) * h->nsf * 3 : nullptr;
+    double* nu = want_nu ? h->nu_f + size_t(k - 1) * h->nsf * rbc::kDiag : nullptr;
     RBC_HIPCHK(h, hipMemcpyAsync(h->Fbuf + (k - 1) * fs, U + (k - 1) * fs, size_t(na) * fs * 8,
                                  hipMemcpyDeviceToDevice, h->stream));
     const bool f64 = k >= kF64;
@@ -152,10 +183,18 @@ rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, i
     if ((s = read_defect(h, k, S + 1, &defect, &bad)) != RBC_OK) return s;
     defect_hist[k - 1] = defect;
     *k_done = k;
-    if (want_nu && (s = nu_average(h, h->nu_f, h->nsf, h->p.nu_stride, h->fine.dt, nu_hist + 3 * k)) != RBC_OK)
+    if (want_nu && (s = diag_average(h, h->nu_f, h->nsf, h->p.nu_stride, h->fine.dt, h->fine.dev.nu,
+                                     nu_hist + rbc::kDiagAvg * k)) != RBC_OK)
       return s;
     if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
-    if (defect <= tol) break;
+    if (defect <= tol) {
+      h->stop_reason = RBC_STOP_DEFECT;
+      break;
+    }
+    if (want_nu && stats_converged(h, nu_hist + rbc::kDiagAvg * k, nu_hist + rbc::kDiagAvg * (k - 1))) {
+      h->stop_reason = RBC_STOP_STATISTICS;
+      break;
+    }
     if (kG64 == INT_MAX && promote_now(h, k, defect, prev, tol)) {
       kG64 = k + 1;
       kF64 = k + 2;
@@ -163,7 +202,8 @@ rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, i
     prev = defect;
   }
   h->k_fp64 = (kF64 <= k) ? kF64 : 0;
-  if (k < S && !(defect <= tol) && tol > 0) return RBC_NOT_CONVERGED;
+  if (h->stop_reason == RBC_STOP_KMAX && k == S) h->stop_reason = RBC_STOP_EXACT;
+  if (h->stop_reason == RBC_STOP_KMAX && tol > 0) return RBC_NOT_CONVERGED;
   return RBC_OK;
 }
 
@@ -413,9 +453,9 @@ int Pipeline::fine_step() {
   }
   ++t_;
   if (want_nu_ && t_ % stride_ == 0 &&
-      !ok(rbc::launch_nusselt_ring(h_->fine, h_->Xring, jobs_[ja_].slot, jn_ - ja_, cap_, h_->meta, t_, stride_,
-                                   h_->nsf, S_, h_->nu_f, F_),
-          "nusselt"))
+      !ok(rbc::launch_diag(h_->fine, h_->wf, h_->Xring, jobs_[ja_].slot, jn_ - ja_, cap_, h_->nu_f, 0, h_->meta, t_,
+                           stride_, h_->nsf, S_, F_),
+          "diagnostics"))
     return -1;
   while (ja_ < jn_ && jobs_[ja_].start + nf_ == t_) {
     if (!ok(hipEventRecord(ev_done_[ja_], F_), "hipEventRecord")) return -1;
@@ -462,13 +502,13 @@ int Pipeline::coarse_work() {
       }
       if (want_nu_) {
         double* nuF = pin + 2;
-        double* nuC = nuF + size_t(2) * S_ * h_->nsf * 3;
+        double* nuC = nuF + size_t(2) * S_ * h_->nsf * rbc::kDiag;
         if (T.k == 0 && h_->nsc > 0 &&
-            !ok(hipMemcpyAsync(nuC, h_->nu_c, size_t(S_) * h_->nsc * 3 * 8, hipMemcpyDeviceToHost, G_),
+            !ok(hipMemcpyAsync(nuC, h_->nu_c, size_t(S_) * h_->nsc * rbc::kDiag * 8, hipMemcpyDeviceToHost, G_),
                 "hipMemcpyAsync"))
           return -1;
         if (T.k >= 1 &&
-            !ok(hipMemcpyAsync(nuF, h_->nu_f, size_t(2) * S_ * h_->nsf * 3 * 8, hipMemcpyDeviceToHost, G_),
+            !ok(hipMemcpyAsync(nuF, h_->nu_f, size_t(2) * S_ * h_->nsf * rbc::kDiag * 8, hipMemcpyDeviceToHost, G_),
                 "hipMemcpyAsync"))
           return -1;
       }
@@ -491,7 +531,8 @@ int Pipeline::coarse_work() {
   // step and runs with Nu samples are launched directly; the rest replay
   // the graph
   const int C = rbc::kCoarseGraphSteps;
-  double* nu = (T.kind == kPredict && want_nu_ && h_->nu_c) ? h_->nu_c + size_t(T.n) * h_->nsc * 3 : nullptr;
+  double* nu =
+      (T.kind == kPredict && want_nu_ && h_->nu_c) ? h_->nu_c + size_t(T.n) * h_->nsc * rbc::kDiag : nullptr;
   hipGraphExec_t gx = g64 ? h_->cgraph64 : h_->cgraph;
   if (gstep_ > 0 && !nu && gx && gstep_ + C <= nc_ - 1) {
     if (!ok(hipGraphLaunch(gx, G_), "hipGraphLaunch")) return -1;
@@ -535,14 +576,14 @@ int Pipeline::poll_report() {
   processed_ = k;
   const double* pin = h_->host_pin;
   const double* nuF = pin + 2;
-  const double* nuC = nuF + size_t(2) * S_ * h_->nsf * 3;
+  const double* nuC = nuF + size_t(2) * S_ * h_->nsf * rbc::kDiag;
   if (k == 0) {
     if (want_nu_) {
       if (h_->nsc > 0)
-        nu_average_host(h_, h_->nsc, h_->stride_c, h_->coarse.dt,
-                        [&](int n) { return nuC + size_t(n) * h_->nsc * 3; }, nu_hist_);
+        diag_average_host(h_, h_->nsc, h_->stride_c, h_->coarse.dt, h_->coarse.dev.nu,
+                          [&](int n) { return nuC + size_t(n) * h_->nsc * rbc::kDiag; }, nu_hist_);
       else
-        nu_hist_[0] = nu_hist_[1] = nu_hist_[2] = NAN;
+        for (int c = 0; c < rbc::kDiagAvg; ++c) nu_hist_[c] = NAN;
     }
     if (K_ == 0) stop_ = true;
     return 1;
@@ -554,18 +595,28 @@ int Pipeline::poll_report() {
   if (want_nu_) {
     // slice n's latest run: iteration k for n >= k-1, else iteration n+1
     const int nsf = h_->nsf;
-    nu_average_host(h_, nsf, stride_, h_->fine.dt,
-                    [&](int n) {
-                      const int par = (n >= k - 1) ? (k & 1) : ((n + 1) & 1);
-                      return nuF + (size_t(par) * S_ + n) * nsf * 3;
-                    },
-                    nu_hist_ + 3 * k);
+    diag_average_host(h_, nsf, stride_, h_->fine.dt, h_->fine.dev.nu,
+                      [&](int n) {
+                        const int par = (n >= k - 1) ? (k & 1) : ((n + 1) & 1);
+                        return nuF + (size_t(par) * S_ + n) * nsf * rbc::kDiag;
+                      },
+                      nu_hist_ + rbc::kDiagAvg * k);
   }
   if (bad) {
     seterr(RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
     return 1;
   }
-  if (defect_ <= tol_ || k == K_) {
+  if (defect_ <= tol_) {
+    h_->stop_reason = RBC_STOP_DEFECT;
+    stop_ = true;
+    return 1;
+  }
+  if (want_nu_ && stats_converged(h_, nu_hist_ + rbc::kDiagAvg * k, nu_hist_ + rbc::kDiagAvg * (k - 1))) {
+    h_->stop_reason = RBC_STOP_STATISTICS;
+    stop_ = true;
+    return 1;
+  }
+  if (k == K_) {
     stop_ = true;
     return 1;
   }
@@ -612,6 +663,7 @@ void Pipeline::fine_loop() {
 rbc_status Pipeline::run() {
   using clk = std::chrono::steady_clock;
   *k_done_ = 0;
+  h_->stop_reason = RBC_STOP_KMAX;
   rbc_status s = setup();
   if (s != RBC_OK) return s;
   // both streams start after the caller's work
@@ -676,7 +728,8 @@ rbc_status Pipeline::run() {
   if (e1 != hipSuccess || e2 != hipSuccess)
     return fail(h_, RBC_ERR_HIP, std::string("pipelined Parareal: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   h_->k_fp64 = (kF64_ <= *k_done_) ? kF64_.load() : 0;
-  if (*k_done_ < S_ && !(defect_ <= tol_) && tol_ > 0) return RBC_NOT_CONVERGED;
+  if (h_->stop_reason == RBC_STOP_KMAX && *k_done_ == S_) h_->stop_reason = RBC_STOP_EXACT;
+  if (h_->stop_reason == RBC_STOP_KMAX && tol_ > 0) return RBC_NOT_CONVERGED;
   return RBC_OK;
 }
 
@@ -705,6 +758,7 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
   if (!h || !U || !k_done || !defect_hist) return fail(h, RBC_ERR_ARG, "null argument");
   if (k_max < 0) return fail(h, RBC_ERR_ARG, "k_max < 0");
   h->k_fp64 = 0;
+  h->stop_reason = -1;
   if (!h->p.pipelined) return parareal_sequential(h, U, k_max, tol, k_done, defect_hist, nu_hist);
   const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
   Pipeline pl(h, U, std::min<int>(k_max, h->p.n_slices), tol, want_nu, k_done, defect_hist, nu_hist);
@@ -714,6 +768,12 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
 rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out) {
   if (!h || !out) return fail(h, RBC_ERR_ARG, "null argument");
   *out = h->pstats;
+  return RBC_OK;
+}
+
+rbc_status rbc_stop_reason(rbc_handle h, int32_t* reason) {
+  if (!h || !reason) return fail(h, RBC_ERR_ARG, "null argument");
+  *reason = h->stop_reason;
   return RBC_OK;
 }
 

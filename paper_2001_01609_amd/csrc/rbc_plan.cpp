@@ -425,7 +425,8 @@ size_t work_bytes(const GridPlan& g, int cap) {
   size_t nh = size_t(cap) * 2 * g.Pz * padded_modes(g) * 2 * rb + size_t(cap) * g.Pz * rb;
   size_t eh = size_t(g.tab.s) * cap * st * rb;
   size_t ly = size_t(g.tab.s - 1) * cap * st * 8;
-  return q + nh + eh + ly + 4 * 256;
+  size_t dp = size_t(cap) * ((g.Mx + diag_modes(g.Nz) - 1) / diag_modes(g.Nz)) * 4 * 8;
+  return q + nh + eh + ly + dp + 5 * 256;
 }
 
 hipError_t alloc_work(const GridPlan& g, int cap, Work& w) {
@@ -438,6 +439,8 @@ hipError_t alloc_work(const GridPlan& g, int cap, Work& w) {
   if ((e = hipMalloc(&w.qbar, size_t(cap) * g.Pz * rb)) != hipSuccess) return e;
   if ((e = hipMalloc(&w.Ehist, size_t(g.tab.s) * cap * st * rb)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.LYhist, size_t(g.tab.s - 1) * cap * st * 8)) != hipSuccess) return e;
+  const size_t nchunk = (g.Mx + diag_modes(g.Nz) - 1) / diag_modes(g.Nz);
+  if ((e = hipMalloc((void**)&w.dpart, size_t(cap) * nchunk * 4 * 8)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -447,6 +450,7 @@ void free_work(Work& w) {
   if (w.qbar) (void)hipFree(w.qbar);
   if (w.Ehist) (void)hipFree(w.Ehist);
   if (w.LYhist) (void)hipFree(w.LYhist);
+  if (w.dpart) (void)hipFree(w.dpart);
   w = Work{};
 }
 

@@ -26,6 +26,11 @@ RBC_ERR_NONFINITE = -4
 RBC_ERR_STATE = -5
 RBC_FP64 = 0
 RBC_MIXED = 1
+RBC_DIAG = 6
+RBC_DIAG_AVG = 9
+DIAG_FIELDS = ("Nu_V", "Nu_b", "Nu_t", "KE", "eps_U", "P")
+DIAG_AVG_FIELDS = ("Nu_V", "Nu_b", "Nu_t", "Nu_int", "KE", "Re", "eps_U", "P", "balance")
+RBC_STOP_DEFECT, RBC_STOP_STATISTICS, RBC_STOP_KMAX, RBC_STOP_EXACT = 0, 1, 2, 3
 RBC_ARS222 = 2
 RBC_ARS443 = 4
 
@@ -51,6 +56,7 @@ class rbc_params(ctypes.Structure):
         ("T_bot", ctypes.c_double), ("T_top", ctypes.c_double),
         ("promote_fp64", ctypes.c_int32),
         ("pipelined", ctypes.c_int32),
+        ("stat_tol", ctypes.c_double),
     ]
 
 
@@ -86,6 +92,8 @@ def _load():
         "parareal_iterate": (st, [vp, vp, i32, dbl, P(i32), P(dbl), P(dbl)]),
         "rbc_nusselt": (st, [vp, vp, i32, P(dbl)]),
         "rbc_fine_fp64_from": (st, [vp, P(i32)]),
+        "rbc_stop_reason": (st, [vp, P(i32)]),
+        "rbc_diagnostics": (st, [vp, vp, i32, P(dbl)]),
         "rbc_explicit_terms": (st, [vp, vp, vp]),
         "rbc_kernel_timing_enable": (st, [vp, i32, i32]),
         "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64), P(dbl)]),
@@ -173,16 +181,31 @@ def rbc_coarse_sweep(h, mode: int, first_slice: int, U, F, G, want_defect: bool 
 
 
 def parareal_iterate(h, U, k_max: int, tol: float, want_nu: bool = False):
-    """Returns (status, k_done, defects[k_done], nu_avg[k_done+1, 3] or None)."""
+    """Returns (status, k_done, defects[k_done], averages[k_done+1, RBC_DIAG_AVG]
+    or None); the averages' columns are DIAG_AVG_FIELDS."""
     k = ctypes.c_int32()
     defects = np.zeros(max(k_max, 1))
-    nu = np.full((k_max + 1, 3), np.nan) if want_nu else None
+    nu = np.full((k_max + 1, RBC_DIAG_AVG), np.nan) if want_nu else None
     st = _check(_lib.parareal_iterate(
         h, _ptr(U), k_max, tol, ctypes.byref(k),
         defects.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_nu else None), h)
     kd = k.value
     return st, kd, defects[:kd].copy(), (nu[: kd + 1].copy() if want_nu else None)
+
+
+def rbc_stop_reason(h) -> int:
+    r = ctypes.c_int32()
+    _check(_lib.rbc_stop_reason(h, ctypes.byref(r)), h)
+    return r.value
+
+
+def rbc_diagnostics(h, U, n_states: int) -> np.ndarray:
+    """[n_states, RBC_DIAG] records (columns DIAG_FIELDS)."""
+    out = np.zeros((max(n_states, 1), RBC_DIAG))
+    _check(_lib.rbc_diagnostics(h, _ptr(U), n_states,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
+    return out[:n_states]
 
 
 def rbc_fine_fp64_from(h) -> int:

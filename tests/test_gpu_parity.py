@@ -346,7 +346,7 @@ def test_parareal_stops_at_tolerance_and_tracks_nu():
         assert defects[-1] <= 1e-3
     assert np.all(np.isfinite(nu[1:]))
     # Nu_V, Nu_b, Nu_t of the fine trajectory are near each other and >= 1
-    assert np.all(nu[1:] > 0.99)
+    assert np.all(nu[1:, :3] > 0.99)
 
 
 @pytest.mark.parametrize("w", [I.C2, I.C2_FP64])
@@ -409,3 +409,82 @@ def test_parareal_promotes_stalled_mixed_fine_sweeps_to_fp64():
     finally:
         R().rbc_destroy(h)
     assert rel(got, ref) < 1e-8
+
+
+# ------------------------------------------- consistency checks (section 2.2) ---
+
+@pytest.mark.parametrize("Nx,Nz", [(32, 16), (64, 8), (64, 64), (8, 256)])
+def test_diagnostic_records_match_oracle(Nx, Nz):
+    """rbc_diagnostics (exact Chebyshev product integrals on the GPU) against
+    the oracle's quadratures: Nu_V, Nu_b, Nu_t, KE, epsilon_U, P; one
+    partly filled mode chunk (32x16, 64x8) and several chunks (64x64,
+    8x256)."""
+    p = params(Nx, Nz, Ra=1e5, dt=2e-3, S=3)
+    case(f"diagnostics {Nx}x{Nz}, 3 states")
+    g = grid(p)
+    Xs = [oracle_state(g, sd, 0.5, steps=5) for sd in (4, 5)] + [O.conduction_state(g)]
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        d = R().rbc_diagnostics(h, U, 3)
+    finally:
+        R().rbc_destroy(h)
+    for i, X in enumerate(Xs):
+        ref = O.diagnostics(g, X)
+        tol = 1e-11 * np.maximum(np.abs(ref), [1, 1, 1, 0, 0, 0]) + 1e-16
+        assert np.all(np.abs(d[i] - ref) <= tol), (i, d[i], ref)
+    assert np.allclose(d[2], [1, 1, 1, 0, 0, 0], atol=1e-14)
+
+
+def test_parareal_time_averages_follow_the_definitions():
+    """After finite termination (k = S) the averaged records of the last
+    iteration are those of the serial fine run: samples from
+    rbc_fine_step_batch, averaged by the oracle's definitions of Re, Nu_int
+    and the balance check."""
+    p = _tiny_parareal_params()
+    p.nu_stride = 5
+    S = p.n_slices
+    case("parareal time averages vs oracle definitions")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(16, g.Nx, g.Nz), 0.3).pack()
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        nf, dt = R().rbc_steps_per_slice(h, 0)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        st, kd, defects, avg = R().parareal_iterate(h, U, S, 0.0, want_nu=True)
+        assert kd == S and R().rbc_stop_reason(h) == R().RBC_STOP_EXACT
+        V = to_dev(U0)
+        rec = []
+        for _ in range(S):
+            smp = torch.zeros((nf // 5) * 6, dtype=torch.float64, device=dev())
+            R().rbc_fine_step_batch(h, V, V, 1, nf, smp)
+            rec.append(smp.view(-1, 6).cpu().numpy())
+    finally:
+        R().rbc_destroy(h)
+    ref = O.time_averages(grid(p, dt), np.concatenate(rec))
+    assert np.allclose(avg[S], ref, rtol=1e-12, atol=1e-15), (avg[S], ref)
+
+
+def test_parareal_statistics_based_stop():
+    """A loose stat_tol stops the iteration once the averaged Nusselt
+    numbers settle, before the defect criterion; the reason is reported."""
+    p = _tiny_parareal_params()
+    p.nu_stride = 5
+    p.stat_tol = 0.05
+    case("parareal statistics-based stop")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(17, g.Nx, g.Nz), 0.3).pack()
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        st, kd, defects, avg = R().parareal_iterate(h, U, p.n_slices, 1e-14, want_nu=True)
+        reason = R().rbc_stop_reason(h)
+    finally:
+        R().rbc_destroy(h)
+    assert st == R().RBC_OK and reason == R().RBC_STOP_STATISTICS, (st, reason, kd, avg[:, :3])
+    assert 1 <= kd < p.n_slices
+    assert np.all(np.abs(avg[kd, :3] - avg[kd - 1, :3]) <= 0.05 * np.abs(avg[kd, :3]))

@@ -52,7 +52,7 @@ def run(p, pipelined, U0, k_max, tol, want_nu):
         U[:n] = torch.tensor(U0, dtype=torch.float64, device=dev())
         st, kd, defects, nu = R().parareal_iterate(h, U, k_max, tol, want_nu=want_nu)
         kp = R().rbc_fine_fp64_from(h)
-        return st, kd, defects, nu, kp, U.cpu().numpy()
+        return st, kd, defects, nu, kp, U.cpu().numpy(), R().rbc_stop_reason(h)
     finally:
         R().rbc_destroy(h)
 
@@ -73,6 +73,9 @@ CASES = {
     # abandoned
     "stop_at_tol": dict(p=dict(Nx=32, Nz=16, Nx_c=16, Nz_c=8, S=6, dt=0.02, dt_c=0.05, t_end=3.0, mixed=True,
                                nu_stride=5), k_max=6, tol=1e-3),
+    # statistics-based stop
+    "stat_stop": dict(p=dict(Nx=32, Nz=16, Nx_c=16, Nz_c=8, S=6, dt=0.02, dt_c=0.05, t_end=3.0, mixed=True,
+                             nu_stride=5, stat_tol=0.05), k_max=6, tol=1e-14),
     # prediction only
     "k0": dict(p=dict(Nx=32, Nz=16, Nx_c=16, Nz_c=8, S=4, dt=0.02, dt_c=0.05, t_end=2.0, mixed=False,
                       nu_stride=5), k_max=0, tol=0.0),
@@ -93,7 +96,7 @@ def test_pipelined_equals_sweep_then_batch_bitwise(name):
     assert np.array_equal(a[2], b[2]), (a[2], b[2])
     if want_nu:
         assert np.array_equal(a[3], b[3], equal_nan=True), (a[3], b[3])
-    assert a[4] == b[4]
+    assert a[4] == b[4] and a[6] == b[6]
     assert np.array_equal(a[5], b[5])
     if name == "mixed_promote":
         assert b[4] > 0, "the FP64 switch did not happen"
