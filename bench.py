@@ -73,9 +73,10 @@ def xpass_bytes_per_dof_step(s: int, rb: int) -> float:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per stage-kernel launch from the committed PMC summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
-    summary is for another workload or the kernel source has changed since."""
+    """HBM bytes per state of a stage-kernel launch from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy, over the states
+    of the profiled launches), or None when the summary is for another
+    workload or the kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
     src = os.path.join(ROOT, "paper_2001_01609_amd", "csrc", "rbc_kernels.hip")
@@ -91,7 +92,7 @@ def measured_traffic(workload: str):
         cur = hashlib.sha256(f.read()).hexdigest()[:16]
     if kv.get("workload") != workload or kv.get("kernel_source_sha256_16") != cur:
         return None
-    return float(kv["bytes_per_launch"])
+    return float(kv["bytes_per_launch"]) / float(kv["states_per_launch"])
 
 
 def cpu_baseline(w, seconds: float):
@@ -202,6 +203,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the Parareal vs serial FP64 time-to-solution comparison")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the sweep-then-batch run and the full-batch fine propagator (profiling: the "
+                         "fine kernels then run only in the timed pipelined run)")
     ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
                     help="counter-collection mode: only N batched fine steps (same kernels and launch "
                          "shapes as the timed run), no Parareal iteration, no JSON line")
@@ -234,9 +238,14 @@ def main() -> int:
         U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
 
         def calibrate():
+            # reference kernels of known traffic for the HBM byte counters:
+            # a fill (writes N bytes), an elementwise scale by 1 into another
+            # buffer (reads N, writes N) and the runtime's device copy
             if args.calibrate_copy > 0:
                 a = torch.empty(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
                 b = torch.empty_like(a)
+                a.fill_(1.0)
+                torch.mul(a, 1.0, out=b)
                 b.copy_(a)
                 torch.cuda.synchronize()
                 del a, b
@@ -275,6 +284,9 @@ def main() -> int:
         finite = bool(np.isfinite(u_pipe).all())
         # fine propagator alone at full batch (events around one batched F
         # call; the stage kernel timed inside it as well)
+        if args.no_compare:
+            return emit(args, w, K, el, kd, defects, nu_hist, finite, k_ms, k_cnt, k_batch, pstats, nf, ncs,
+                        None, None)
         F = U[:S * n].clone()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         R.rbc_kernel_timing_enable(h, 0, TIMING_EVERY)
@@ -289,6 +301,7 @@ def main() -> int:
     finally:
         R.rbc_destroy(h)
     # the same K iterations in the sweep-then-batch order (same results, bit for bit)
+    seq = None
     q = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0, pipelined=0)
     h = R.rbc_create(q, stream.cuda_stream)
     try:
@@ -299,10 +312,18 @@ def main() -> int:
         R.parareal_iterate(h, U, K, 0.0, want_nu=True)
         torch.cuda.synchronize()
         el_seq = time.perf_counter() - t0
-        same = bool(np.array_equal(U.cpu().numpy(), u_pipe))
+        seq = (el_seq, bool(np.array_equal(U.cpu().numpy(), u_pipe)))
         print(f"[bench] sweep-then-batch Parareal: {K} iterations in {el_seq:.2f} s", file=sys.stderr, flush=True)
     finally:
         R.rbc_destroy(h)
+    return emit(args, w, K, el, kd, defects, nu_hist, finite, k_ms, k_cnt, k_batch, pstats, nf, ncs,
+                seq, (f_ms, kf_ms, kf_cnt, kf_batch))
+
+
+def emit(args, w, K, el, kd, defects, nu_hist, finite, k_ms, k_cnt, k_batch, pstats, nf, ncs, seq, full):
+    """Prints the JSON line (the timed run's figures and the optional legs)."""
+    from paper_2001_01609_amd import rbc as R
+    S = w.n_slices
 
     dof = w.Nx * w.Nz
     runs = sum(S - k + 1 for k in range(1, K + 1))      # fine runs of iterations 1..K
@@ -310,11 +331,10 @@ def main() -> int:
     value = fine_dof_steps / el
     rb = 4 if w.mixed else 8
     s = w.scheme
-    per_launch = stage_kernel_bytes_per_dof_step(s, rb) / s * dof * k_batch
+    per_state = stage_kernel_bytes_per_dof_step(s, rb) / s * dof
+    per_launch = per_state * k_batch
     achieved = per_launch / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
-    full_launch = stage_kernel_bytes_per_dof_step(s, rb) / s * dof * kf_batch
-    achieved_full = full_launch / (kf_ms * 1e-3) / 1e9 if kf_ms > 0 else 0.0
-    traffic = measured_traffic(w.name)
+    traffic_state = measured_traffic(w.name)
     out = {
         "metric": "fine-step DOF-steps/s (%HBM roofline); Parareal vs serial time-to-solution",
         "value": value,
@@ -336,23 +356,30 @@ def main() -> int:
                            "prediction and `steps` iterations from the seeded state, fine runs of "
                            "iteration k on slices k-1..S-1)"},
         "roofline": {"bound": "hbm", "kernel": "stage_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_state * k_batch if traffic_state else None,
                      "bytes_per_launch": per_launch, "mean_launch_ms": k_ms, "timed_launches": k_cnt,
                      "mean_slices_per_launch": k_batch},
-        "fine_propagator": {"dof_steps_per_s": dof * S * nf / (f_ms * 1e-3), "ms_per_call": f_ms,
-                            "us_per_batched_step": 1e3 * f_ms / nf, "slices": S,
-                            "stage_kernel": {"mean_launch_ms": kf_ms, "timed_launches": kf_cnt,
-                                             "bytes_per_launch": full_launch, "achieved_gbs": achieved_full,
-                                             "frac": achieved_full / HBM_PEAK_GBS},
-                            "bytes_per_dof_step_model": stage_kernel_bytes_per_dof_step(s, rb) +
-                            xpass_bytes_per_dof_step(s, rb)},
         "parareal": {"iterations": kd, "defects": [float(d) for d in defects], "fine_runs": runs,
                      "averages_last": {f: float(v) for f, v in zip(R.DIAG_AVG_FIELDS, nu_hist[-1])},
                      "finite": finite,
-                     "sweep_then_batch_s": el_seq, "sweep_then_batch_value": fine_dof_steps / el_seq,
-                     "pipelined_speedup": el_seq / el, "bitwise_equal_to_sweep_then_batch": same,
                      "scheduler": {k: v for k, v in pstats.items() if k != "report_at_s"}},
     }
+    if seq is not None:
+        el_seq, same = seq
+        out["parareal"].update({"sweep_then_batch_s": el_seq, "sweep_then_batch_value": fine_dof_steps / el_seq,
+                                "pipelined_speedup": el_seq / el, "bitwise_equal_to_sweep_then_batch": same})
+    if full is not None:
+        f_ms, kf_ms, kf_cnt, kf_batch = full
+        achieved_full = per_state * kf_batch / (kf_ms * 1e-3) / 1e9 if kf_ms > 0 else 0.0
+        out["fine_propagator"] = {
+            "dof_steps_per_s": dof * S * nf / (f_ms * 1e-3), "ms_per_call": f_ms,
+            "us_per_batched_step": 1e3 * f_ms / nf, "slices": S,
+            "stage_kernel": {"mean_launch_ms": kf_ms, "timed_launches": kf_cnt,
+                             "bytes_per_launch": per_state * kf_batch, "achieved_gbs": achieved_full,
+                             "frac": achieved_full / HBM_PEAK_GBS,
+                             "traffic": traffic_state * kf_batch if traffic_state else None},
+            "bytes_per_dof_step_model": stage_kernel_bytes_per_dof_step(s, rb) + xpass_bytes_per_dof_step(s, rb)}
     if not args.no_tts:
         out["time_to_solution"] = time_to_solution(w)
     if args.cpu_seconds > 0:
