@@ -202,6 +202,14 @@ rbc_status parareal_iterate(rbc_handle h, double* U_dev, int32_t k_max, double t
                             int32_t* k_done_host, double* defect_hist_host,
                             double* nu_avg_hist_host);
 
+/* Iterate history for studies of the convergence (section 4): later
+ * parareal_iterate calls copy U_dev ([n_slices+1][state]) after the coarse
+ * prediction and after each iteration k <= k_cap into
+ * U_hist_dev[k][n_slices+1][state] (device memory of (k_cap+1) (n_slices+1)
+ * states, caller-owned).  NULL disables.  With k = n_slices the last copy is
+ * the serial fine solution at every slice boundary. */
+rbc_status rbc_set_iterate_history(rbc_handle h, double* U_hist_dev, int32_t k_cap);
+
 /* Why the last parareal_iterate stopped (rbc_stop; -1 before any). */
 rbc_status rbc_stop_reason(rbc_handle h, int32_t* reason);
 
@@ -215,14 +223,14 @@ rbc_status rbc_fine_fp64_from(rbc_handle h, int32_t* k_host);
  * enqueueing coarse work, reading reports and waiting for the device; the
  * number of batched fine steps and of coarse chunks enqueued; the mean
  * number of fine runs per batched step; the wall time of the call, and the
- * wall time at which the report of iteration k was read (k = 0..15, the
+ * wall time at which the report of iteration k was read (k = 0..63, the
  * rest unset).  All zero before the first pipelined call. */
 typedef struct {
   double wall_s;
   double host_admit_s, host_fine_s, host_coarse_s, host_report_s, host_wait_s;
   int64_t fine_steps, coarse_chunks;
   double mean_runs_per_step;
-  double report_at_s[16];
+  double report_at_s[64];
 } rbc_pipeline_stats;
 rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out);
 

@@ -18,6 +18,8 @@ struct rbc_ctx {
   bool has64 = false;
   int k_fp64 = 0;              // first iteration the last parareal_iterate ran F in FP64 (0: never)
   int stop_reason = -1;        // of the last parareal_iterate (rbc_stop_reason)
+  double* U_hist = nullptr;    // iterate history (rbc_set_iterate_history)
+  int hist_cap = -1;
   rbc::Work wf, wc, wf64, wc64;  // fine work for ring_cap slices, coarse work for one
   int nf = 0, nc = 0;          // steps per slice
   int ring_cap = 0;            // fine state slots: n_slices + 2

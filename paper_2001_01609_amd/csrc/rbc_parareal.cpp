@@ -135,6 +135,14 @@ bool stats_converged(rbc_handle h, const double* cur, const double* prev) {
   return true;
 }
 
+// Copies U after iteration k into the iterate history when one is set.
+rbc_status save_iterate(rbc_handle h, const double* U, int k, hipStream_t st) {
+  if (!h->U_hist || k > h->hist_cap) return RBC_OK;
+  const size_t n = size_t(h->p.n_slices + 1) * h->fine.dev.state;
+  RBC_HIPCHK(h, hipMemcpyAsync(h->U_hist + size_t(k) * n, U, n * 8, hipMemcpyDeviceToDevice, st));
+  return RBC_OK;
+}
+
 // The precision switch of promote_fp64, decided after iteration k (defect
 // d, previous defect prev): the coarse sweeps switch from k + 1, the fine
 // runs from k + 2.
@@ -152,6 +160,7 @@ rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, i
   rbc_status s;
   *k_done = 0;
   if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
+  if ((s = save_iterate(h, U, 0, h->stream)) != RBC_OK) return s;
   if (want_nu) {
     if (h->nsc > 0) {
       if ((s = diag_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, h->coarse.dev.nu, nu_hist)) != RBC_OK)
@@ -179,6 +188,7 @@ rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, i
     RBC_HIPCHK(h, rbc::launch_combine(h->fine, h->coarse, 2, U + k * fs, h->Fbuf + (k - 1) * fs, nullptr, nullptr,
                                       h->part + size_t(k) * rbc::kCombineBlocks * 2, h->stream));
     if ((s = sweep(h, 1, k, U, h->Fbuf, h->Gbuf, false, k >= kG64)) != RBC_OK) return s;
+    if ((s = save_iterate(h, U, k, h->stream)) != RBC_OK) return s;
     bool bad = false;
     if ((s = read_defect(h, k, S + 1, &defect, &bad)) != RBC_OK) return s;
     defect_hist[k - 1] = defect;
@@ -496,6 +506,12 @@ int Pipeline::coarse_work() {
     }
     if (T.kind == kReport) {
       double* pin = h_->host_pin;
+      if (h_->U_hist && T.k <= h_->hist_cap) {
+        const size_t n = size_t(S_ + 1) * fs_;
+        if (!ok(hipMemcpyAsync(h_->U_hist + size_t(T.k) * n, U_, n * 8, hipMemcpyDeviceToDevice, G_),
+                "hipMemcpyAsync"))
+          return -1;
+      }
       if (T.k >= 1) {
         if (!ok(rbc::launch_defect(h_->part, T.k, S_ + 1, h_->dscal, G_), "defect")) return -1;
         if (!ok(hipMemcpyAsync(pin, h_->dscal, 16, hipMemcpyDeviceToHost, G_), "hipMemcpyAsync")) return -1;
@@ -690,7 +706,7 @@ rbc_status Pipeline::run() {
     const auto t1 = clk::now();
     ps.host_report_s += std::chrono::duration<double>(t1 - tp).count();
     if (r < 0) break;
-    if (processed_ != processed_before && processed_ >= 0 && processed_ < 16)
+    if (processed_ != processed_before && processed_ >= 0 && processed_ < 64)
       ps.report_at_s[processed_] = std::chrono::duration<double>(t1 - t_start).count();
     if (stop_.load()) break;
     const int c = coarse_work();
@@ -768,6 +784,14 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
 rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out) {
   if (!h || !out) return fail(h, RBC_ERR_ARG, "null argument");
   *out = h->pstats;
+  return RBC_OK;
+}
+
+rbc_status rbc_set_iterate_history(rbc_handle h, double* U_hist, int32_t k_cap) {
+  if (!h) return RBC_ERR_ARG;
+  if (U_hist && k_cap < 0) return fail(h, RBC_ERR_ARG, "k_cap < 0");
+  h->U_hist = U_hist;
+  h->hist_cap = U_hist ? k_cap : -1;
   return RBC_OK;
 }
 

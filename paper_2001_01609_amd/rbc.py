@@ -68,7 +68,7 @@ class rbc_pipeline_stats(ctypes.Structure):
         ("host_wait_s", ctypes.c_double),
         ("fine_steps", ctypes.c_int64), ("coarse_chunks", ctypes.c_int64),
         ("mean_runs_per_step", ctypes.c_double),
-        ("report_at_s", ctypes.c_double * 16),
+        ("report_at_s", ctypes.c_double * 64),
     ]
 
 
@@ -93,6 +93,7 @@ def _load():
         "rbc_nusselt": (st, [vp, vp, i32, P(dbl)]),
         "rbc_fine_fp64_from": (st, [vp, P(i32)]),
         "rbc_stop_reason": (st, [vp, P(i32)]),
+        "rbc_set_iterate_history": (st, [vp, vp, i32]),
         "rbc_diagnostics": (st, [vp, vp, i32, P(dbl)]),
         "rbc_explicit_terms": (st, [vp, vp, vp]),
         "rbc_kernel_timing_enable": (st, [vp, i32, i32]),
@@ -192,6 +193,11 @@ def parareal_iterate(h, U, k_max: int, tol: float, want_nu: bool = False):
         nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_nu else None), h)
     kd = k.value
     return st, kd, defects[:kd].copy(), (nu[: kd + 1].copy() if want_nu else None)
+
+
+def rbc_set_iterate_history(h, U_hist, k_cap: int) -> None:
+    """U_hist: device float64 tensor of (k_cap + 1) (n_slices + 1) states, or None."""
+    _check(_lib.rbc_set_iterate_history(h, _ptr(U_hist) if U_hist is not None else None, k_cap), h)
 
 
 def rbc_stop_reason(h) -> int:

@@ -102,3 +102,40 @@ def test_pipelined_equals_sweep_then_batch_bitwise(name):
         assert b[4] > 0, "the FP64 switch did not happen"
     if name == "stop_at_tol":
         assert b[1] < p.n_slices and b[2][-1] <= 1e-3
+
+
+@pytest.mark.parametrize("pipelined", [0, 1])
+def test_iterate_history(pipelined):
+    """rbc_set_iterate_history: U after the prediction and after every
+    iteration; slices 0..k of iterate k equal the serial fine solution bit
+    for bit, and the last iterate is the returned state."""
+    S = 4
+    p = params(32, 16, 16, 8, S, 0.02, 0.05, 2.0, False)
+    p.pipelined = pipelined
+    case(f"iterate history, pipelined={pipelined}")
+    g = O.Grid(p.Ra, p.Pr, p.Lx, p.Lz, p.Nx, p.Nz, p.dt_f)
+    U0 = O.initial_state(g, I.gaussian_noise(33, g.Nx, g.Nz), 0.3).pack()
+    h = R().rbc_create(p, torch.cuda.current_stream(dev()).cuda_stream)
+    try:
+        n = R().rbc_state_size(h)
+        nf, _ = R().rbc_steps_per_slice(h, 0)
+        hist = torch.zeros((S + 1) * (S + 1) * n, dtype=torch.float64, device=dev())
+        R().rbc_set_iterate_history(h, hist, S)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = torch.tensor(U0, dtype=torch.float64, device=dev())
+        R().parareal_iterate(h, U, S, 0.0)
+        serial = [torch.tensor(U0, dtype=torch.float64, device=dev())]
+        for _ in range(S):
+            v = serial[-1].clone()
+            R().rbc_fine_step_batch(h, v, v, 1, nf)
+            serial.append(v)
+        H = hist.view(S + 1, S + 1, n).cpu().numpy()
+        ser = torch.stack(serial).cpu().numpy()
+        u = U.view(S + 1, n).cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    for k in range(S + 1):
+        for nn in range(k + 1):
+            assert np.array_equal(H[k][nn], ser[nn]), (k, nn)
+    assert np.array_equal(H[S], u)
+    assert not np.array_equal(H[1], H[2])
