@@ -7,7 +7,8 @@ shares no code with it.
 What it computes (each function names the part of the paper it follows):
 
 * the Oberbeck-Boussinesq equations of section 2.1 (Eqs. 1-3) with the
-  fixed-temperature, no-slip walls of Eq. 4, written in free-fall units on
+  no-slip walls of fixed temperature (Eq. 4) or fixed flux (Eq. 5, with
+  the flux Rayleigh number Ra_f in place of Ra), written in free-fall units on
   z in [0, Lz] (the reading used for the workloads: viscosity sqrt(Pr/Ra),
   diffusivity 1/sqrt(Ra Pr), buoyancy coefficient 1), in the
   streamfunction-vorticity form so that the pressure drops out;
@@ -152,7 +153,9 @@ class Grid:
 
     Ra, Pr: Rayleigh and Prandtl numbers (section 2.1); Lx, Lz: box size
     (aspect ratio 2 in the paper); Nx, Nz: collocation points (section 3.2);
-    dt: time step; scheme: 2 or 4 (see ars_tableau).
+    dt: time step; scheme: 2 or 4 (see ars_tableau).  flux: fixed-flux
+    walls dT/dz = -1 (Eq. 5; Ra is then the flux Rayleigh number Ra_f)
+    instead of the fixed temperatures T_bot, T_top (Eq. 4).
     """
     Ra: float
     Pr: float
@@ -164,6 +167,7 @@ class Grid:
     scheme: int = 4
     T_bot: float = 1.0   # temperature at z = 0 (Eq. 4)
     T_top: float = 0.0   # temperature at z = Lz (Eq. 4)
+    flux: bool = False   # fixed-flux walls (Eq. 5)
 
     def __post_init__(self):
         if self.Nx % 4 or self.Nz % 2:
@@ -243,21 +247,27 @@ class State:
 def initial_state(g: Grid, xi: np.ndarray, amp: float) -> State:
     """Linear conduction profile plus a small perturbation, u = 0
     (section 2.1): T = T_bot + (T_top - T_bot) z/Lz + amp xi z(Lz - z)/Lz^2
-    on the Nx x Nz collocation grid, transformed; psi = u_bar = 0.
+    (fixed flux: T = T_bot - z + the same perturbation) on the Nx x Nz
+    collocation grid, transformed; psi = u_bar = 0.
     ``xi`` is the [Nx, Nz] standard-normal noise from the seeded generator."""
     x, z = grid_points(g)
     zz = z[None, :] / g.Lz
-    Tg = g.T_bot + (g.T_top - g.T_bot) * zz + amp * xi * zz * (1.0 - zz)
+    base = g.T_bot - z[None, :] if g.flux else g.T_bot + (g.T_top - g.T_bot) * zz
+    Tg = base + amp * xi * zz * (1.0 - zz)
     T = from_grid(Tg, g.Mx, g.Nz)
     T[0] = T[0].real
     return State(T, np.zeros_like(T))
 
 
 def conduction_state(g: Grid) -> State:
-    """T = T_bot + (T_top - T_bot) z / Lz, no flow."""
+    """T = T_bot + (T_top - T_bot) z / Lz (fixed flux: T_bot - z), no flow."""
     T = np.zeros((g.Mx, g.Nz), dtype=np.complex128)
-    T[0, 0] = 0.5 * (g.T_bot + g.T_top)
-    T[0, 1] = 0.5 * (g.T_top - g.T_bot)
+    if g.flux:
+        T[0, 0] = g.T_bot - 0.5 * g.Lz
+        T[0, 1] = -0.5 * g.Lz
+    else:
+        T[0, 0] = 0.5 * (g.T_bot + g.T_top)
+        T[0, 1] = 0.5 * (g.T_top - g.T_bot)
     return State(T, np.zeros_like(T))
 
 
@@ -310,14 +320,14 @@ def bc_rows(N: int, scale: float, kind: str) -> np.ndarray:
     """Boundary rows (tau method) on coefficient vectors.
 
     kind 'dirichlet': value at zeta = -1 (z = 0) and at zeta = +1 (z = Lz),
-    T_n(+-1) = (+-1)^n.  kind 'clamped': additionally d/dz at both walls,
-    T_n'(1) = n^2, T_n'(-1) = (-1)^(n+1) n^2, times scale.
+    T_n(+-1) = (+-1)^n.  kind 'neumann': d/dz at both walls,
+    T_n'(1) = n^2, T_n'(-1) = (-1)^(n+1) n^2, times scale.  kind 'clamped':
+    the dirichlet rows, then the neumann rows.
     """
     n = np.arange(N, dtype=np.float64)
-    rows = [(-1.0) ** n, np.ones(N)]
-    if kind == "clamped":
-        rows += [(-1.0) ** (n + 1) * n * n * scale, n * n * scale]
-    return np.array(rows)
+    value = [(-1.0) ** n, np.ones(N)]
+    slope = [(-1.0) ** (n + 1) * n * n * scale, n * n * scale]
+    return np.array({"dirichlet": value, "neumann": slope, "clamped": value + slope}[kind])
 
 
 class StageSolver:
@@ -328,7 +338,8 @@ class StageSolver:
     def __init__(self, g: Grid, ops: Operators, h_aii: float):
         N = g.Nz
         self.g = g
-        self.bT = bc_rows(N, g.scale, "dirichlet")
+        self.bT = bc_rows(N, g.scale, "neumann" if g.flux else "dirichlet")
+        self.bU = bc_rows(N, g.scale, "dirichlet")          # no-slip mean flow
         self.bP = bc_rows(N, g.scale, "clamped")
         self.luT, self.luP = [], []
         for m in range(g.Mx):
@@ -340,7 +351,7 @@ class StageSolver:
             if m == 0:
                 M, L = ops.U_ops()
                 A = M - h_aii * L
-                A[N - 2:] = self.bT
+                A[N - 2:] = self.bU
             else:
                 M, L = ops.P_ops(k)
                 A = M - h_aii * L
@@ -355,7 +366,7 @@ class StageSolver:
         N = self.g.Nz
         r = rhs.copy()
         if m == 0:
-            r[N - 2:] = [self.g.T_bot, self.g.T_top]
+            r[N - 2:] = [-1.0, -1.0] if self.g.flux else [self.g.T_bot, self.g.T_top]
         else:
             r[N - 2:] = 0.0
         return self._solve(self.luT[m], r)
@@ -494,7 +505,10 @@ class Stepper:
 
 
 def nusselt(g: Grid, X: State):
-    """(Nu_V, Nu_b, Nu_t) of Eqs. 8-10, in free-fall units.
+    """(Nu_V, Nu_b, Nu_t) of Eqs. 8-10, in free-fall units, each divided by
+    the conductive flux of the current mean temperature drop, dT / Lz with
+    dT = <T>_H(z=0) - <T>_H(z=Lz) (1 for the fixed temperatures of Eq. 4;
+    for the fixed flux of Eq. 5 this is the Nu = 1 / dT of that case).
 
     Nu_b, Nu_t: -dT/dz of the horizontal mean at z = 0 and z = Lz (exact
     endpoint derivatives of the Chebyshev series).
@@ -523,8 +537,9 @@ def nusselt(g: Grid, X: State):
 
     wT = np.mean(phys(w_hat) * phys(X.T), axis=0)
     mean_wT = 0.5 * np.sum(wl * wT)
-    nu_v = (T_z0 - T_z1) / g.Lz + math.sqrt(g.Ra * g.Pr) * mean_wT
-    return nu_v, nu_b, nu_t
+    ref = (T_z0 - T_z1) / g.Lz                         # conductive flux of the drop
+    nu_v = ((T_z0 - T_z1) / g.Lz + math.sqrt(g.Ra * g.Pr) * mean_wT) / ref
+    return nu_v, nu_b / ref, nu_t / ref
 
 
 def kinetic_energy(g: Grid, X: State) -> float:

@@ -281,10 +281,11 @@ def test_nonlinear_self_convergence_order(scheme, order):
 
 # ---------------------------------------------------- linear onset (P6) ---
 
-def _growth_rate(Ra, k, Nz=24):
+def _growth_rate(Ra, k, Nz=24, flux=False):
     """Largest real eigenvalue of the linearised problem built from the
     oracle's operators (conduction background, free-fall units).
-    Unknowns (phi, T) with psi = i phi so that the pencil is real."""
+    Unknowns (phi, T) with psi = i phi so that the pencil is real.  flux:
+    fixed-flux walls (the temperature perturbation has zero wall slope)."""
     Lx = 2 * np.pi / k
     g = O.Grid(Ra, 1.0, Lx, 1.0, 4, Nz, 1.0)
     ops = O.Operators(g)
@@ -303,7 +304,7 @@ def _growth_rate(Ra, k, Nz=24):
     A[N - 4:N, :N] = O.bc_rows(N, g.scale, "clamped")
     B[N - 4:N, :] = 0
     A[2 * N - 2:, :] = 0
-    A[2 * N - 2:, N:] = O.bc_rows(N, g.scale, "dirichlet")
+    A[2 * N - 2:, N:] = O.bc_rows(N, g.scale, "neumann" if flux else "dirichlet")
     B[2 * N - 2:, :] = 0
     w = scipy.linalg.eig(A, B, right=False)
     w = w[np.isfinite(w)]
@@ -566,3 +567,63 @@ def test_time_averages_of_the_consistency_checks():
     assert abs(a[4] - 0.05) < 1e-15
     assert abs(a[5] - (0.2 + 0.4) / 2 / g.nu) < 1e-12 * a[5]
     assert np.allclose(a[6:8], [0.0071, 0.0071]) and a[8] < 1e-12
+
+
+
+# ------------------------------------------------ fixed-flux walls (Eq. 5) ---
+
+@pytest.mark.parametrize("m", [0, 1, 5])
+def test_tau_solve_recovers_manufactured_temperature_fixed_flux(m):
+    """(1 - h kappa (d_zz - k^2)) T = f with dT/dz = -1 (m = 0) or 0 (m >= 1)
+    on both walls: f built analytically from a polynomial T; the solver
+    returns T."""
+    g = O.Grid(1e4, 1.0, 2.0, 1.0, 16, 20, 0.3, scheme=4, flux=True)
+    ops = O.Operators(g)
+    h_aii = 0.3 * 0.5
+    k = g.k[m]
+    z2 = np.polynomial.Polynomial([0, 0, 1, -2, 1])       # z^2 (1-z)^2: zero slope at both walls
+    T = np.polynomial.Polynomial([0.4, -1.0 if m == 0 else 0.0]) + z2 * np.polynomial.Polynomial([0.3, -1.2, 0.7])
+    assert abs(T.deriv()(0.0) - (-1.0 if m == 0 else 0.0)) < 1e-14
+    f = T - h_aii * g.kappa * (T.deriv(2) - k * k * T)
+    Tc = _cheb_of(T, g.Lz, g.Nz)
+    rhs = ops.S10 @ _cheb_of(f, g.Lz, g.Nz)
+    sol = O.StageSolver(g, ops, h_aii).solve_T(m, rhs.astype(complex))
+    assert np.allclose(sol, Tc, atol=1e-12)
+
+
+def test_fixed_flux_conduction_state_is_a_fixed_point():
+    g = O.Grid(5e3, 1.0, 2.0, 1.0, 16, 16, 0.05, scheme=4, flux=True)
+    X = O.conduction_state(g)
+    Y = O.Stepper(g).run(X, 20)
+    assert np.abs(Y.pack() - X.pack()).max() < 1e-13
+    assert np.allclose(O.nusselt(g, Y), 1.0, atol=1e-13)
+
+
+def test_nusselt_closed_form_fixed_flux():
+    """Mean profile 1 - z + a cos(pi z) (slope -1 at both walls, drop
+    dT = 1 + 2a) with the flow of test_nusselt_closed_form: Nu_b = Nu_t =
+    1/dT and Nu_V = 1 + sqrt(Ra Pr) <w T> / dT (Nu = 1/dT for fixed flux)."""
+    Ra, a, e, b = 1e5, 0.15, 0.05, 0.03
+    g = O.Grid(Ra, 1.0, 2.0, 1.0, 16, 32, 1.0, flux=True)
+    k = g.k[1]
+    x, z = O.grid_points(g)
+    T = (1 - z + a * np.cos(np.pi * z))[None, :] + e * np.cos(k * x)[:, None] * np.sin(np.pi * z)[None, :]
+    psi = b * np.sin(k * x)[:, None] * (z * z * (1 - z) ** 2)[None, :]
+    X = O.State(O.from_grid(T, g.Mx, g.Nz), O.from_grid(psi, g.Mx, g.Nz))
+    X.P[0] = 0
+    nu_v, nu_b, nu_t = O.nusselt(g, X)
+    dT = 1 + 2 * a
+    assert abs(nu_b - 1 / dT) < 1e-10 and abs(nu_t - 1 / dT) < 1e-10, (nu_b, nu_t)
+    I_, _ = scipy.integrate.quad(lambda s: s * s * (1 - s) ** 2 * np.sin(np.pi * s), 0, 1,
+                                 epsabs=1e-15, epsrel=1e-14)
+    assert abs(nu_v - (1 + math.sqrt(Ra) * (-e * b * k / 2) * I_ / dT)) < 1e-10
+
+
+def test_fixed_flux_onset_tends_to_720():
+    """Rigid, perfectly conducting-flux (insulating) walls: the critical
+    Rayleigh number of the long-wave limit is 720 (Hurle, Jakeman & Pike
+    1967), approached as Ra_c(k) = 720 + O(k^2)."""
+    ra = [scipy.optimize.brentq(lambda R: _growth_rate(R, kk, flux=True), 600, 900, xtol=1e-8)
+          for kk in (0.04, 0.02)]
+    assert abs(ra[1] - 720.0) < 0.05, ra
+    assert ra[0] > ra[1] > 720.0 - 1e-6 and abs((ra[0] - 720) / (ra[1] - 720) - 4) < 0.1, ra
