@@ -61,7 +61,10 @@ typedef enum {
 typedef enum { RBC_FP64 = 0, RBC_MIXED = 1 } rbc_precision;
 
 /* Diagnostic record of one state (section 2.2), RBC_DIAG doubles:
- *   Nu_V (Eq. 8), Nu_b (Eq. 9), Nu_t (Eq. 10), KE = <u^2 + w^2>/2,
+ *   Nu_V (Eq. 8), Nu_b (Eq. 9), Nu_t (Eq. 10), each divided by the
+ *   conductive flux dT/Lz of the current mean temperature drop dT = <T>(z=0)
+ *   - <T>(z=Lz) (dT = 1 for fixed temperatures; Nu = 1/dT for fixed flux),
+ *   KE = <u^2 + w^2>/2,
  *   epsilon_U = nu <|grad u|^2> (viscous dissipation), P = <w T> (buoyancy
  *   production), all volume means in free-fall units, exact for the
  *   discrete fields.  Time averages, RBC_DIAG_AVG doubles:
@@ -79,6 +82,11 @@ typedef enum {
   RBC_STOP_EXACT = 3        /* k = n_slices: the serial fine solution           */
 } rbc_stop;
 typedef enum { RBC_ARS222 = 2, RBC_ARS443 = 4 } rbc_scheme;
+/* Temperature walls: fixed temperatures T_bot, T_top (Eq. 4) or fixed flux
+ * dT/dz = -1 at both walls (Eq. 5; Ra is then the flux Rayleigh number Ra_f,
+ * T_top is unused and the initial profile is T_bot - z).  The velocity is
+ * no-slip in both. */
+typedef enum { RBC_BC_TEMPERATURE = 0, RBC_BC_FLUX = 1 } rbc_bc;
 
 /* Problem and discretisation.  Section 2.1 gives the equations and the
  * box (aspect ratio 2), section 3.2 the grid, sections 3.6-3.7 the coarse
@@ -120,6 +128,7 @@ typedef struct {
                               iteration k >= 1, stop when each time-averaged
                               Nu_V, Nu_b, Nu_t changed by <= stat_tol
                               (relative) from iteration k-1.  0 = off.      */
+  int32_t bc_T;            /* rbc_bc (default RBC_BC_TEMPERATURE)           */
 } rbc_params;
 
 /* Fill p with defaults (T_bot = 1, T_top = 0, ARS443, FP64, no sampling). */

@@ -59,6 +59,7 @@ std::string check_params(const rbc_params* p) {
   if (p->precision != RBC_FP64 && p->precision != RBC_MIXED) return "precision must be RBC_FP64 or RBC_MIXED";
   if (p->nu_stride < 0) return "nu_stride must be >= 0";
   if (!(p->stat_tol >= 0)) return "stat_tol must be >= 0";
+  if (p->bc_T != RBC_BC_TEMPERATURE && p->bc_T != RBC_BC_FLUX) return "bc_T must be RBC_BC_TEMPERATURE or RBC_BC_FLUX";
   return "";
 }
 
@@ -72,6 +73,7 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.Ra = p->Ra; g.Pr = p->Pr; g.Lx = p->Lx; g.Lz = p->Lz;
   g.dt = dt;
   g.T_bot = p->T_bot; g.T_top = p->T_top;
+  g.flux = (p->bc_T == RBC_BC_FLUX);
   g.scheme = coarse ? p->scheme_c : p->scheme_f;
   g.mixed = (p->precision == RBC_MIXED);
   // modes per block of the per-mode kernel (2, 4, 6 or 8); RBC_MODE_TILE overrides
@@ -310,7 +312,8 @@ rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double amp, double* U0) {
       const double u1 = unif(2 * pidx), u2 = unif(2 * pidx + 1);
       const double xi = std::sqrt(-2.0 * std::log(1.0 - u1)) * std::cos(2.0 * M_PI * u2);
       const double z = zj[iz];
-      Tg[size_t(ix) * Nz + iz] = g.T_bot + (g.T_top - g.T_bot) * z + amp * xi * z * (1.0 - z);
+      const double base = g.flux ? g.T_bot - z * g.Lz : g.T_bot + (g.T_top - g.T_bot) * z;
+      Tg[size_t(ix) * Nz + iz] = base + amp * xi * z * (1.0 - z);
     }
   // Fourier in x (modes m < Mx, 1/Nx normalisation), Chebyshev in z
   std::vector<double> cs(Nx), sn(Nx);

@@ -52,6 +52,8 @@ struct GridDev {
   double nu, kappa, scale;        // viscosity, diffusivity, dzeta/dz = 2/Lz
   double Lz, sqrtRaPr;
   double T_bot, T_top;
+  double bcT[2];                  // m = 0 temperature wall values per parity (wall rows of the plan)
+  int fluxT;                      // 1: temperature wall rows are slopes (fixed flux)
   const double* bS10;             // [2][n][3]  S1S0 rows, half offsets 0..2
   const double* bD2;              // [2][n]     D2 rows, half offset 1
   const double* bA;               // [2][n][3]  S3S2D2 rows, half offsets 1..3
@@ -71,6 +73,7 @@ struct GridPlan {
   int Nx = 0, Nz = 0, Mx = 0, Px = 0, Pz = 0, n = 0;
   double Ra = 0, Pr = 0, Lx = 0, Lz = 0, dt = 0, nu = 0, kappa = 0, scale = 0;
   double T_bot = 1, T_top = 0;
+  bool flux = false;              // fixed-flux temperature walls (Eq. 5)
   int scheme = 4;
   Tableau tab;
   int MT = 8;

@@ -272,9 +272,17 @@ __host__ __device__ __forceinline__ int lds_fac_stride(int s) { return s | 1; }
 // vector is held in registers for the three sweeps (shorter dependent chain,
 // more registers: the latency-bound small-batch variant); otherwise the
 // sweeps run in LDS.
+// Weight of tail unknown i (coefficient n = 2 (i + 1) + p) in the wall row
+// of a bordered tridiagonal system: 1 for wall values, n^2 for wall slopes
+// (fixed-flux temperature walls).
+__device__ __forceinline__ double wall_w(int i, int p, bool slope) {
+  const double n = double(2 * (i + 1) + p);
+  return slope ? n * n : 1.0;
+}
+
 template <int NR, bool REG>
 __device__ __forceinline__ void solve_T_format(double* __restrict__ v, int p, const double* __restrict__ fac,
-                                               double gbc) {
+                                               double gbc, bool slope) {
   if constexpr (REG && NR <= 31) {
     double y[NR + 1];
 #pragma unroll
@@ -283,11 +291,11 @@ __device__ __forceinline__ void solve_T_format(double* __restrict__ v, int p, co
     for (int i = 1; i < NR; ++i) y[i] -= fac[i * kFacT + 0] * y[i - 1];
     double sum = 0;
     y[NR - 1] *= fac[(NR - 1) * kFacT + 1];
-    sum = y[NR - 1];
+    sum = wall_w(NR - 1, p, slope) * y[NR - 1];
 #pragma unroll
     for (int i = NR - 2; i >= 0; --i) {
       y[i] = (y[i] - fac[i * kFacT + 2] * y[i + 1]) * fac[i * kFacT + 1];
-      sum += y[i];
+      sum += wall_w(i, p, slope) * y[i];
     }
     const double xh = fac[NR * kFacT] * (gbc - sum);
     v[p] = xh;
@@ -302,12 +310,12 @@ __device__ __forceinline__ void solve_T_format(double* __restrict__ v, int p, co
     }
     double x = y * fac[(NR - 1) * kFacT + 1];
     v[2 * (NR - 1) + p] = x;
-    double sum = x;
+    double sum = wall_w(NR - 1, p, slope) * x;
 #pragma unroll 8
     for (int i = NR - 2; i >= 0; --i) {
       x = (v[2 * i + p] - fac[i * kFacT + 2] * x) * fac[i * kFacT + 1];
       v[2 * i + p] = x;
-      sum += x;
+      sum += wall_w(i, p, slope) * x;
     }
     const double xh = fac[NR * kFacT] * (gbc - sum);
 #pragma unroll 8
@@ -392,7 +400,7 @@ __device__ __forceinline__ double seg_sum(double x) {
 
 template <int NR, int W>
 __device__ __forceinline__ void solve_T_scan(double* __restrict__ v, int p, const double* __restrict__ fac,
-                                             double gbc, int li) {
+                                             double gbc, bool slope, int li) {
   const bool act = li < NR;
   const double* fr = fac + li * kFacT;
   const double f = act ? v[2 * li + p] : 0.0;
@@ -421,7 +429,7 @@ __device__ __forceinline__ void solve_T_scan(double* __restrict__ v, int p, cons
       A = A * An;
     }
   }
-  const double sum = seg_sum<W>(B);
+  const double sum = seg_sum<W>(wall_w(li, p, slope) * B);
   const double xh = fac[NR * kFacT] * (gbc - sum);
   if (act) v[2 * (li + 1) + p] = B - vc * xh;
   if (li == 0) v[p] = xh;
@@ -903,9 +911,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
           if (m < Mx) {
             double gbc = 0.0;
-            if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
+            if (m == 0 && ri == 0) gbc = g.bcT[p];
             solve_T_scan<NRT, WS>(sY + ((MT + mt) * 2 + ri) * LD, p,
-                                  sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc, li);
+                                  sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc, g.fluxT != 0, li);
           }
         }
       }
@@ -913,9 +921,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       const int mt = tid >> 2, p = (tid >> 1) & 1, ri = tid & 1, m = m0 + mt;
       if (m < Mx) {
         double gbc = 0.0;
-        if (m == 0 && ri == 0) gbc = (p == 0) ? 0.5 * (g.T_top + g.T_bot) : 0.5 * (g.T_top - g.T_bot);
+        if (m == 0 && ri == 0) gbc = g.bcT[p];
         solve_T_format<NRT, kWide>(sY + ((MT + mt) * 2 + ri) * LD, p,
-                                   sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc);
+                                   sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc, g.fluxT != 0);
       }
     }
     __syncthreads();
@@ -948,7 +956,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
             const double* fac = sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
             double* v = sY + (mt * 2 + ri) * LD;
             if (m == 0)
-              solve_T_scan<NRT, WS>(v, p, fac, 0.0, li);
+              solve_T_scan<NRT, WS>(v, p, fac, 0.0, false, li);
             else
               solve_P_scan<NRP, WS>(v, p, fac, li);
           }
@@ -960,7 +968,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         const double* fac = sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
         double* v = sY + (mt * 2 + ri) * LD;
         if (m == 0)
-          solve_T_format<NRT, kWide>(v, p, fac, 0.0);
+          solve_T_format<NRT, kWide>(v, p, fac, 0.0, false);
         else
           solve_P_format<NRP, kWide>(v, p, fac);
       }
@@ -1320,9 +1328,10 @@ __global__ void diag_final_kernel(GridDev g, const double* __restrict__ X, int s
     t0 += tm[n] * sgn;
     t1 += tm[n];
   }
-  o[0] = (t0 - t1) / g.Lz + g.sqrtRaPr * v[0];   // Nu_V
-  o[1] = -g.scale * nb;                          // Nu_b
-  o[2] = -g.scale * nt;                          // Nu_t
+  const double ref = (t0 - t1) / g.Lz;           // conductive flux of the mean temperature drop
+  o[0] = ((t0 - t1) / g.Lz + g.sqrtRaPr * v[0]) / ref;   // Nu_V
+  o[1] = -g.scale * nb / ref;                            // Nu_b
+  o[2] = -g.scale * nt / ref;                            // Nu_t
   o[3] = 0.5 * (v[1] + v[2]);                    // KE
   o[4] = g.nu * v[3];                            // epsilon_U
   o[5] = v[0];                                   // P = <w T>

@@ -12,7 +12,8 @@
 //   u_bar (m=0)  M = S1S0,                  L = nu D2
 // Every stage of the ARS schemes solves (M - h a_ii L) y = r with the last
 // rows replaced by wall conditions.  Split by parity, each system is
-//   [ C ]        C: 1 or 2 dense wall rows  (sum of coefficients, sum of n^2 c_n)
+//   [ C ]        C: 1 or 2 dense wall rows  (sum of coefficients, sum of n^2 c_n;
+//                fixed-flux temperature walls: sum of n^2 c_n alone)
 //   [ R ] y = f  R: banded rows, half-column offsets 0..w (w = 2 or 4)
 // It is solved by bordering: with the first b unknowns as the border,
 // R = [R1 | R2] and R2 square banded (b sub-, w-b super-diagonals),
@@ -274,8 +275,12 @@ std::string build_plan(GridPlan& g) {
                 k2 * (1.0 + haii * g.nu * k2) * o.S3210[e] - haii * g.nu * o.D4[e];
     }
     for (int p = 0; p < 2; ++p) {
-      std::vector<double> C1(n, 1.0);
-      double gr = factor_bordered(parity_rows(AT, N, p, nrT), nrT, n, 1, 1, C1,
+      // wall row of one parity: values (T(1) +- T(-1))/2 = sum c_n, or for
+      // fixed flux slopes (T'(1) -+ T'(-1))/2 = sum n^2 c_n
+      std::vector<double> C1(n, 1.0), CT(n, 1.0);
+      if (g.flux)
+        for (int c = 0; c < n; ++c) CT[c] = double(2 * c + p) * double(2 * c + p);
+      double gr = factor_bordered(parity_rows(AT, N, p, nrT), nrT, n, 1, 1, CT,
                                   &g.facT[(size_t(m) * 2 + p) * g.facT_stride], kFacT, err);
       if (!err.empty()) return err + " (temperature, mode " + std::to_string(m) + ")";
       g.max_growth = std::fmax(g.max_growth, gr);
@@ -401,6 +406,12 @@ hipError_t upload_plan(GridPlan& g) {
   d.nu = g.nu; d.kappa = g.kappa; d.scale = g.scale; d.Lz = g.Lz;
   d.sqrtRaPr = std::sqrt(g.Ra * g.Pr);
   d.T_bot = g.T_bot; d.T_top = g.T_top;
+  // right-hand sides of the m = 0 temperature wall rows per parity: values
+  // (T_top +- T_bot)/2, or for fixed flux the zeta-slopes (0, -Lz/2) of
+  // dT/dz = -1 at both walls
+  d.bcT[0] = g.flux ? 0.0 : 0.5 * (g.T_top + g.T_bot);
+  d.bcT[1] = g.flux ? -0.5 * g.Lz : 0.5 * (g.T_top - g.T_bot);
+  d.fluxT = g.flux ? 1 : 0;
   d.bS10 = reinterpret_cast<const double*>(base + offs[0]);
   d.bD2 = reinterpret_cast<const double*>(base + offs[1]);
   d.bA = reinterpret_cast<const double*>(base + offs[2]);

@@ -26,6 +26,7 @@ RBC_ERR_NONFINITE = -4
 RBC_ERR_STATE = -5
 RBC_FP64 = 0
 RBC_MIXED = 1
+RBC_BC_TEMPERATURE, RBC_BC_FLUX = 0, 1
 RBC_DIAG = 6
 RBC_DIAG_AVG = 9
 DIAG_FIELDS = ("Nu_V", "Nu_b", "Nu_t", "KE", "eps_U", "P")
@@ -57,6 +58,7 @@ class rbc_params(ctypes.Structure):
         ("promote_fp64", ctypes.c_int32),
         ("pipelined", ctypes.c_int32),
         ("stat_tol", ctypes.c_double),
+        ("bc_T", ctypes.c_int32),
     ]
 
 

@@ -60,7 +60,8 @@ def create(p):
 
 
 def grid(p, dt=None):
-    return O.Grid(p.Ra, p.Pr, p.Lx, p.Lz, p.Nx, p.Nz, dt if dt is not None else p.dt_f, scheme=p.scheme_f)
+    return O.Grid(p.Ra, p.Pr, p.Lx, p.Lz, p.Nx, p.Nz, dt if dt is not None else p.dt_f, scheme=p.scheme_f,
+                  flux=(p.bc_T == R().RBC_BC_FLUX))
 
 
 def oracle_state(g, seed, amp, steps=0):
@@ -488,3 +489,88 @@ def test_parareal_statistics_based_stop():
     assert st == R().RBC_OK and reason == R().RBC_STOP_STATISTICS, (st, reason, kd, avg[:, :3])
     assert 1 <= kd < p.n_slices
     assert np.all(np.abs(avg[kd, :3] - avg[kd - 1, :3]) <= 0.05 * np.abs(avg[kd, :3]))
+
+
+
+# ---------------------------------------------- fixed-flux walls (Eq. 5) ---
+
+def test_init_state_fixed_flux_matches_oracle():
+    p = params(32, 16, Ra=1e5, dt=2e-3, bc_T=R().RBC_BC_FLUX)
+    case("init_state fixed flux")
+    h = create(p)
+    try:
+        U = torch.zeros(R().rbc_state_size(h), dtype=torch.float64, device=dev())
+        R().rbc_init_state(h, 3, 1e-2, U)
+        got = U.cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    g = grid(p)
+    ref = O.initial_state(g, I.gaussian_noise(3, g.Nx, g.Nz), 1e-2).pack()
+    assert np.abs(got - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("Nx,Nz,mixed", [(16, 8, False), (32, 16, False), (64, 32, False), (32, 16, True)])
+def test_steps_fixed_flux_match_oracle(Nx, Nz, mixed):
+    """Fixed-flux walls: 5 fine steps and the diagnostic record against the
+    oracle (FP64 1e-12, mixed 1e-6)."""
+    p = params(Nx, Nz, Ra=2e4, dt=5e-3, mixed=mixed, bc_T=R().RBC_BC_FLUX)
+    case(f"fixed flux {Nx}x{Nz} mixed={mixed}")
+    g = grid(p)
+    X = oracle_state(g, 7, 0.3, steps=3)
+    h = create(p)
+    try:
+        U = to_dev(X.pack())
+        R().rbc_fine_step_batch(h, U, U, 1, 5)
+        d = R().rbc_diagnostics(h, U, 1)[0]
+        got = U.cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    Y = O.Stepper(g).run(X, 5)
+    assert rel(got, Y.pack()) < (1e-6 if mixed else 1e-12)
+    ref = O.diagnostics(g, Y)
+    tol = (1e-5 if mixed else 1e-11) * np.maximum(np.abs(ref), [1, 1, 1, 0, 0, 0]) + 1e-16
+    assert np.all(np.abs(d - ref) <= tol), (d, ref)
+    # the wall slope stays -1 in the mean profile: Nu_b = Nu_t = 1 / dT
+    assert abs(d[1] - d[2]) < 1e-10
+
+
+def test_conduction_state_fixed_point_fixed_flux_on_gpu():
+    for mixed in (False, True):
+        p = params(32, 16, Ra=1e5, dt=1e-2, mixed=mixed, bc_T=R().RBC_BC_FLUX)
+        case(f"fixed-flux conduction fixed point mixed={mixed}")
+        g = grid(p)
+        X = O.conduction_state(g).pack()
+        h = create(p)
+        try:
+            U = to_dev(X)
+            R().rbc_fine_step_batch(h, U, U, 1, 20)
+            nu = R().rbc_nusselt(h, U, 1)[0]
+            got = U.cpu().numpy()
+        finally:
+            R().rbc_destroy(h)
+        # the slope wall row weighs coefficients by n^2: rounding, not drift
+        assert np.abs(got - X).max() < 1e-13
+        assert np.allclose(nu, 1.0, atol=1e-13)
+
+
+def test_parareal_fixed_flux_matches_oracle_iterates():
+    p = params(32, 16, Ra=3e3, dt=0.02, scheme=4, S=4, Nx_c=16, Nz_c=8, t_end=2.0, dt_c=0.05,
+               bc_T=R().RBC_BC_FLUX)
+    case("parareal fixed flux vs oracle")
+    fine = grid(p)
+    coarse = O.Grid(p.Ra, p.Pr, p.Lx, p.Lz, p.Nx_c, p.Nz_c, p.dt_c, scheme=p.scheme_c, flux=True)
+    pp = O.RBCParareal(fine, coarse, p.t0, p.t_end, p.n_slices)
+    U0 = O.initial_state(fine, I.gaussian_noise(19, fine.Nx, fine.Nz), 0.3).pack()
+    ref = pp.run(U0, k_max=2)
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        st, kd, defects, _ = R().parareal_iterate(h, U, 2, 0.0)
+        got = U.cpu().numpy().reshape(p.n_slices + 1, -1)
+    finally:
+        R().rbc_destroy(h)
+    for nn in range(p.n_slices + 1):
+        assert rel(got[nn], ref.U[nn]) < FP64_TOL, nn
+    assert np.allclose(defects, ref.defects, rtol=1e-8, atol=1e-14)
