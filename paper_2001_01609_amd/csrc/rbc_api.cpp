@@ -74,6 +74,11 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.dt = dt;
   g.T_bot = p->T_bot; g.T_top = p->T_top;
   g.flux = (p->bc_T == RBC_BC_FLUX);
+  // The coarse sweep is serial and runs beside the batched fine launches on
+  // the same compute units: its waves take the SIMD issue slots first.
+  // RBC_COARSE_PRIO=0 turns this off (for measurement).
+  g.urgent = coarse;
+  if (const char* e = std::getenv("RBC_COARSE_PRIO")) g.urgent = coarse && std::atoi(e) != 0;
   g.scheme = coarse ? p->scheme_c : p->scheme_f;
   g.mixed = (p->precision == RBC_MIXED);
   // modes per block of the per-mode kernel (2, 4, 6 or 8); RBC_MODE_TILE overrides

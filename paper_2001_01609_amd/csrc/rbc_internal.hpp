@@ -54,6 +54,7 @@ struct GridDev {
   double T_bot, T_top;
   double bcT[2];                  // m = 0 temperature wall values per parity (wall rows of the plan)
   int fluxT;                      // 1: temperature wall rows are slopes (fixed flux)
+  int urgent;                     // 1: waves run at raised SIMD issue priority (coarse grid)
   const double* bS10;             // [2][n][3]  S1S0 rows, half offsets 0..2
   const double* bD2;              // [2][n]     D2 rows, half offset 1
   const double* bA;               // [2][n][3]  S3S2D2 rows, half offsets 1..3
@@ -74,6 +75,7 @@ struct GridPlan {
   double Ra = 0, Pr = 0, Lx = 0, Lz = 0, dt = 0, nu = 0, kappa = 0, scale = 0;
   double T_bot = 1, T_top = 0;
   bool flux = false;              // fixed-flux temperature walls (Eq. 5)
+  bool urgent = false;            // coarse grid: the serial sweep is the critical path
   int scheme = 4;
   Tableau tab;
   int MT = 8;

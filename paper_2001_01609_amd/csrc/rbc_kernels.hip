@@ -191,6 +191,7 @@ template <typename Real, int PX, int RB>
 __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* __restrict__ Q,
                                                         Real* __restrict__ Nh, Real* __restrict__ qbar,
                                                         int slot0, int cap) {
+  if (g.urgent) __builtin_amdgcn_s_setprio(3);
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = g.Pz, Mx = g.Mx, MT = g.MT, ntile = g.ntile;
   const int ngrp = Pz / RB;
@@ -599,6 +600,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   // their cached loads.)
   constexpr bool kPre = kWide && NZ <= 64;
   static_assert(kBlock % NZ == 0, "NZ must divide the block size");
+  if (g.urgent) __builtin_amdgcn_s_setprio(3);
   extern __shared__ __align__(16) unsigned char smem[];
   const int Mx = g.Mx;
   const int ntile = g.ntile;   // ceil(Mx / MT)
