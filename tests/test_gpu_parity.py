@@ -350,12 +350,13 @@ def test_parareal_stops_at_tolerance_and_tracks_nu():
     assert np.all(nu[1:, :3] > 0.99)
 
 
-@pytest.mark.parametrize("w", [I.C2, I.C2_FP64])
+@pytest.mark.parametrize("w", [I.C2, I.C2_FP64, I.C3])
 def test_fullsize_batch_sampled_slices(w):
-    """The benchmark's shape (32 slices of 256x64): one batched step, slices
-    0 and 31 checked against the oracle."""
+    """Full workload shapes (32 slices of 256x64, the benchmark's; 64 slices
+    of 1024x256): two batched steps, the first and last slices checked
+    against the oracle."""
     p = R().params_from_workload(w)
-    case(f"full size {w.name}: 32 slices, 1 step")
+    case(f"full size {w.name}: {p.n_slices} slices, 2 steps")
     g = grid(p)
     h = create(p)
     try:
@@ -372,8 +373,9 @@ def test_fullsize_batch_sampled_slices(w):
         R().rbc_destroy(h)
     st = O.Stepper(g)
     tol = MIXED_TOL if w.mixed else FP64_TOL
+    last = p.n_slices - 1   # odd: the second initial state
     assert rel(got[0], st.run(X0, 2).pack()) < tol
-    assert rel(got[31], st.run(X1, 2).pack()) < tol
+    assert rel(got[last], st.run(X1, 2).pack()) < tol
 
 
 def test_parareal_promotes_stalled_mixed_fine_sweeps_to_fp64():
