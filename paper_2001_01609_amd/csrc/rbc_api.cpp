@@ -96,7 +96,7 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
     const size_t y = size_t(8) * 4 * mt * (g.Nz + 1);
     const size_t n = rb * (4 * size_t(g.Pz) * mt + g.Pz);
     const size_t f = size_t(8) * mt * 2 * ((rbc::kFacP * (g.Nz / 2 - 2) + 4) | 1);
-    const size_t u = n > f ? n : f, v = rb * size_t(g.Pz) * mt * 12;
+    const size_t u = n > f ? n : f, v = (mt <= 2) ? rb * size_t(g.Pz) * mt * 12 : 0;
     return y + (y + u > v ? y + u : v);
   };
   while (g.MT > 2 && lds(g.MT) > 150 * 1024) g.MT = (g.MT == 6) ? 4 : g.MT / 2;

@@ -550,7 +550,8 @@ __host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool 
   constexpr size_t PZ = 3 * NZ / 2;
   const size_t tile = sizeof(double) * 4 * MT * (NZ + 1);
   const size_t nh = rb * (4 * PZ * MT + PZ);
-  const size_t vals = rb * PZ * MT * 12;
+  // phase G scratch: only the two-pass inverse transform of two-mode tiles
+  const size_t vals = (MT <= 2) ? rb * PZ * MT * 12 : 0;
   StageLds L{};
   if (!pre) {
     const size_t fac = sizeof(double) * size_t(MT) * 2 * size_t((fsT > fsP ? fsT : fsP) | 1);
