@@ -139,7 +139,14 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes);
 
 /* Validate p, build the operator tables and band factorisations on the
  * host, allocate workspaces on the current device; hip_stream may be NULL
- * (the null stream).  On error *out is NULL. */
+ * (the null stream).  On error *out is NULL.
+ * The handle creates two streams of its own for the pipelined iteration.
+ * A process has few hardware queues (four by default), so live handles
+ * beyond the one iterating can leave its two streams on a shared queue,
+ * where they no longer overlap: destroy handles that are done.
+ * Environment, read here (measurement aids): RBC_MODE_TILE = 2, 4, 6 or 8
+ * sets the modes per block of the per-mode kernel; RBC_COARSE_PRIO = 0
+ * keeps the coarse-grid kernels at the default wave priority. */
 rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out);
 rbc_status rbc_destroy(rbc_handle h);
 
