@@ -181,6 +181,16 @@ __device__ __forceinline__ Real wave_sum(Real v) {
   return v;
 }
 
+// Complex spectra of length PX held in LDS per x-pass row: three (the
+// packed pairs (u, w), (omega_x, omega_z), (T_x, T_z) transformed together),
+// or two for multi-row FP64 blocks up to PX = 768, where LDS bounds the rows
+// per CU: (T_x, T_z) is then transformed after N_omega has gone to registers,
+// in the second spectrum's place.
+template <typename Real, int PX, int RB>
+constexpr int xpass_spectra() {
+  return (sizeof(Real) == 8 && PX <= 768 && RB > 1) ? 2 : 3;
+}
+
 // One block of RB wavefronts per (slice, group of RB padded z points); wave w
 // transforms row j = RB group + w.  Q holds the six fields of the stage at
 // the padded Gauss points and Nh receives N_omega and N_T, both mode-tile
@@ -199,37 +209,74 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
   const int s = ring_slot(b, slot0, cap);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = jg * RB + wv;
-  Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem) + wv * 3 * PX;   // this row's [3][PX]
+  constexpr int NA = xpass_spectra<Real, PX, RB>();
+  Cx<Real>* A = reinterpret_cast<Cx<Real>*>(smem) + wv * NA * PX;   // this row's [NA][PX]
   const Cx<Real>* tw = reinterpret_cast<const Cx<Real>*>(g.tw);
   const size_t tq = size_t(Pz) * MT;                 // complex values per (quantity, tile)
 
-  // the zero padding between the retained modes
+  // the zero padding between the retained modes of spectra c0 .. c1-1
   const int nzc = PX - 2 * Mx + 1;
-  for (int c = 0; c < 3; ++c)
-    for (int t = lane; t < nzc; t += 64) A[c * PX + Mx + t] = {Real(0), Real(0)};
-  // pack (u, w), (omega_x, omega_z), (T_x, T_z) into three complex spectra
   const Cx<Real>* Qc = reinterpret_cast<const Cx<Real>*>(Q) + size_t(s) * 6 * ntile * tq + size_t(j) * MT;
-  for (int m = lane; m < Mx; m += 64) {
-    const int tile = m / MT, mt = m - tile * MT;
-    const Cx<Real>* q0 = Qc + size_t(tile) * tq + mt;
-    Cx<Real> q6[6];
+  // packs the field pairs c0 .. c1-1 of (u, w), (omega_x, omega_z), (T_x,
+  // T_z) into spectra at A + (c - d) PX
+  auto pack = [&](int c0, int c1, int d) {
+    for (int c = c0; c < c1; ++c)
+      for (int t = lane; t < nzc; t += 64) A[(c - d) * PX + Mx + t] = {Real(0), Real(0)};
+    for (int m = lane; m < Mx; m += 64) {
+      const int tile = m / MT, mt = m - tile * MT;
+      const Cx<Real>* q0 = Qc + size_t(tile) * tq + mt;
+      Cx<Real> q6[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) q6[c] = q0[size_t(c) * ntile * tq];
+      for (int c = 0; c < 6; ++c)
+        if (c >= 2 * c0 && c < 2 * c1) q6[c] = q0[size_t(c) * ntile * tq];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const Cx<Real> qa = q6[2 * c], qb = q6[2 * c + 1];
-      A[c * PX + m] = {qa.x - qb.y, qa.y + qb.x};
-      if (m > 0) A[c * PX + PX - m] = {qa.x + qb.y, qb.x - qa.y};
+      for (int c = 0; c < 3; ++c) {
+        if (c < c0 || c >= c1) continue;
+        const Cx<Real> qa = q6[2 * c], qb = q6[2 * c + 1];
+        A[(c - d) * PX + m] = {qa.x - qb.y, qa.y + qb.x};
+        if (m > 0) A[(c - d) * PX + PX - m] = {qa.x + qb.y, qb.x - qa.y};
+      }
     }
-  }
-  __syncthreads();
-  fft_wave<Real, PX, 1, 3>(A, tw, Real(1));
+  };
   Real uw = 0;
-  for (int t = lane; t < PX; t += 64) {
-    const Cx<Real> v1 = A[t], v2 = A[PX + t], v3 = A[2 * PX + t];
-    const Real u = v1.x, w = v1.y;
-    A[t] = {u * v2.x + w * v2.y, u * v3.x + w * v3.y};
-    uw += u * w;
+  if constexpr (NA == 3) {
+    pack(0, 3, 0);
+    __syncthreads();
+    fft_wave<Real, PX, 1, 3>(A, tw, Real(1));
+    for (int t = lane; t < PX; t += 64) {
+      const Cx<Real> v1 = A[t], v2 = A[PX + t], v3 = A[2 * PX + t];
+      const Real u = v1.x, w = v1.y;
+      A[t] = {u * v2.x + w * v2.y, u * v3.x + w * v3.y};
+      uw += u * w;
+    }
+  } else {
+    constexpr int NT = (PX + 63) / 64;
+    Real nw[NT];
+    pack(0, 2, 0);
+    __syncthreads();
+    fft_wave<Real, PX, 1, 2>(A, tw, Real(1));
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int t = lane + 64 * i;
+      nw[i] = Real(0);
+      if (t < PX) {
+        const Cx<Real> v1 = A[t], v2 = A[PX + t];
+        nw[i] = v1.x * v2.x + v1.y * v2.y;
+        uw += v1.x * v1.y;
+      }
+    }
+    __syncthreads();
+    pack(2, 3, 1);   // (T_x, T_z) into the second spectrum
+    __syncthreads();
+    fft_wave<Real, PX, 1, 1>(A + PX, tw, Real(1));
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int t = lane + 64 * i;
+      if (t < PX) {
+        const Cx<Real> v1 = A[t], v3 = A[PX + t];
+        A[t] = {nw[i], v1.x * v3.x + v1.y * v3.y};
+      }
+    }
   }
   uw = wave_sum(uw);
   if (lane == 0) qbar[size_t(s) * Pz + j] = uw / Real(PX);
@@ -1463,7 +1510,7 @@ hipError_t run_stage(const GridPlan& g, Work& w, const StageArgs& a, double* X, 
 // Rows per x-pass block: as many (up to four) as fit in 80 KiB of LDS.
 template <typename Real, int PX>
 constexpr int xpass_rows() {
-  constexpr size_t row = sizeof(Real) * 2 * 3 * size_t(PX);
+  constexpr size_t row = sizeof(Real) * 2 * xpass_spectra<Real, PX, 4>() * size_t(PX);
   return (4 * row <= 80 * 1024) ? 4 : ((2 * row <= 80 * 1024) ? 2 : 1);
 }
 
@@ -1474,11 +1521,11 @@ hipError_t run_xpass_t(const GridPlan& g, Work& w, int slot0, int n_slices, hipS
   // a small batch (the single-slice coarse sweep) would leave most CUs idle
   // with several rows per block: one row per block there
   if (RB > 1 && n_slices * (d.Pz / RB) < 256) {
-    const size_t lds = sizeof(Real) * 2 * 3 * size_t(PX);
+    const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, 1>() * size_t(PX);
     hipLaunchKernelGGL((xpass_kernel<Real, PX, 1>), dim3(n_slices * d.Pz), dim3(64), lds, st, d, (const Real*)w.Q,
                        (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
   } else {
-    const size_t lds = sizeof(Real) * 2 * 3 * size_t(PX) * RB;
+    const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, RB>() * size_t(PX) * RB;
     hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(n_slices * (d.Pz / RB)), dim3(64 * RB), lds, st, d,
                        (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
   }
