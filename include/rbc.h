@@ -140,7 +140,8 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes);
 /* Validate p, build the operator tables and band factorisations on the
  * host, allocate workspaces on the current device; hip_stream may be NULL
  * (the null stream).  On error *out is NULL.
- * The handle creates two streams of its own for the pipelined iteration.
+ * The handle creates two streams of its own for the pipelined iteration
+ * (three with the FP64 switch: precision RBC_MIXED and promote_fp64).
  * A process has few hardware queues (four by default), so live handles
  * beyond the one iterating can leave its two streams on a shared queue,
  * where they no longer overlap: destroy handles that are done.

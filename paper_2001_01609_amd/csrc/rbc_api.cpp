@@ -124,6 +124,7 @@ void release(rbc_handle h) {
   if (h->cgraph64) (void)hipGraphExecDestroy(h->cgraph64);
   if (h->fstream) (void)hipStreamDestroy(h->fstream);
   if (h->gstream) (void)hipStreamDestroy(h->gstream);
+  if (h->f64stream) (void)hipStreamDestroy(h->f64stream);
   if (h->host_pin) (void)hipHostFree(h->host_pin);
   rbc::free_work(h->wf);
   rbc::free_work(h->wc);
@@ -266,9 +267,12 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
   if (hipHostMalloc((void**)&h->host_pin, (2 + (2 * S * h->nsf + S * h->nsc) * rbc::kDiag) * 8, hipHostMallocDefault) !=
       hipSuccess)
     return bail(RBC_ERR_OOM, "pinned host buffer");
-  // the pipelined iteration's two streams (default priority)
+  // the pipelined iteration's streams (default priority): fine runs, coarse
+  // sweep, and with the FP64 switch the FP64 fine runs, which then step
+  // beside the mixed runs still in flight instead of after them
   if ((he = hipStreamCreateWithFlags(&h->fstream, hipStreamNonBlocking)) != hipSuccess ||
-      (he = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking)) != hipSuccess)
+      (he = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking)) != hipSuccess ||
+      (h->has64 && (he = hipStreamCreateWithFlags(&h->f64stream, hipStreamNonBlocking)) != hipSuccess))
     return bail(RBC_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(he));
   *out = h;
   return RBC_OK;

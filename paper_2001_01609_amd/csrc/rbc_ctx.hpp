@@ -12,6 +12,7 @@ struct rbc_ctx {
   hipStream_t stream = nullptr;     // the caller's stream
   hipStream_t fstream = nullptr;    // pipelined Parareal: batched fine runs
   hipStream_t gstream = nullptr;    // pipelined Parareal: serial coarse sweep
+  hipStream_t f64stream = nullptr;  // pipelined Parareal: FP64 fine runs (with the FP64 switch only)
   int device = 0;
   rbc::GridPlan fine, coarse;
   rbc::GridPlan fine64, coarse64;   // all-FP64 plans for promoted sweeps (mixed + promote_fp64)

@@ -26,10 +26,13 @@
 //     iteration k-1 (stop test, precision switch).
 // The jobs of iteration k+1 start before the defect of iteration k is known:
 // after convergence they are abandoned.
-// Two host threads enqueue the work, one per stream (a kernel launch costs
-// the host microseconds, and one thread could not keep both streams fed):
-// the fine thread admits jobs and enqueues batched steps, the calling thread
-// enqueues coarse work and reads the reports.  They share the admission and
+// Two host threads enqueue the work (a kernel launch costs the host
+// microseconds, and one thread could not keep both streams fed): the fine
+// thread admits jobs and enqueues batched steps, the calling thread enqueues
+// coarse work and reads the reports.  With the FP64 switch, FP64 jobs live on
+// a third stream: each batched step then advances the mixed and the FP64
+// jobs in flight concurrently (disjoint slots and work buffers), and a job's
+// events are recorded on its own stream.  They share the admission and
 // completion counters and the coarse task counter (atomics, release on
 // write after the matching event is recorded, acquire on read).
 #include <algorithm>
@@ -238,7 +241,8 @@ class Pipeline {
            double* nu_hist)
       : h_(h), U_(U), S_(h->p.n_slices), K_(K), nf_(h->nf), nc_(h->nc), cap_(h->ring_cap),
         stride_(h->p.nu_stride), tol_(tol), want_nu_(want_nu), k_done_(k_done), defect_hist_(defect_hist),
-        nu_hist_(nu_hist), fs_(h->fine.dev.state), cs_(h->coarse.dev.state), F_(h->fstream), G_(h->gstream) {}
+        nu_hist_(nu_hist), fs_(h->fine.dev.state), cs_(h->coarse.dev.state), F_(h->fstream), G_(h->gstream),
+        F64_(h->f64stream ? h->f64stream : h->fstream) {}
 
   rbc_status run();
 
@@ -252,19 +256,20 @@ class Pipeline {
   double* defect_hist_;
   double* nu_hist_;
   const size_t fs_, cs_;
-  hipStream_t F_, G_;
+  hipStream_t F_, G_, F64_;   // F64_: FP64 fine jobs (F_ when there is no FP64 stream)
 
   std::vector<Job> jobs_;
   std::vector<int> job_base_;    // [K+1]: index of job (k, k-1)
   std::vector<Task> tasks_;
   std::vector<int> task_base_;   // [K+1]: index of Copy(k), k >= 1
   hipEvent_t *ev_admit_ = nullptr, *ev_done_ = nullptr, *ev_task_ = nullptr;
-  hipEvent_t *ev_step_ = nullptr, *ev_chunk_ = nullptr, ev_entry_ = nullptr;
+  hipEvent_t *ev_step_ = nullptr, *ev_step64_ = nullptr, *ev_chunk_ = nullptr, ev_entry_ = nullptr;
 
   // fine thread: writes jn_, ja_ (shared), owns t_, freal_
   std::atomic<int> jn_{0}, ja_{0};   // next job to admit, first unfinished job
   int t_ = 0;                        // virtual fine step
   long freal_ = 0;                   // batched fine steps enqueued
+  long f64real_ = 0;                 // of those, steps with FP64 jobs on F64_
   // coarse thread: writes gi_, kF64_ (shared), owns the rest
   std::atomic<int> gi_{0};           // next coarse task
   int gstep_ = -1;                   // coarse steps enqueued of task gi_ (-1: not started)
@@ -375,7 +380,7 @@ rbc_status Pipeline::setup() {
     for (int n = k; n < S_; ++n) tasks_.push_back({kCorrect, k, n});
     tasks_.push_back({kReport, k, -1});
   }
-  const size_t need = 2 * jobs_.size() + tasks_.size() + kFDepth + kGDepth + 1;
+  const size_t need = 2 * jobs_.size() + tasks_.size() + 2 * kFDepth + kGDepth + 1;
   while (h_->evpool.size() < need) {
     hipEvent_t e;
     RBC_HIPCHK(h_, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -388,6 +393,7 @@ rbc_status Pipeline::setup() {
   ev_done_ = p; p += jobs_.size();
   ev_task_ = p; p += tasks_.size();
   ev_step_ = p; p += kFDepth;
+  ev_step64_ = p; p += kFDepth;
   ev_chunk_ = p; p += kGDepth;
   ev_entry_ = *p;
   return RBC_OK;
@@ -418,9 +424,10 @@ int Pipeline::admit() {
     J.start = t_;
     rbc::GridPlan& fp = J.f64 ? h_->fine64 : h_->fine;
     rbc::Work& fw = J.f64 ? h_->wf64 : h_->wf;
-    if (want_nu_ && !ok(rbc::launch_set_meta(h_->meta, J.slot, {J.k & 1, J.n, J.start, 0}, F_), "set_meta"))
+    hipStream_t js = J.f64 ? F64_ : F_;
+    if (want_nu_ && !ok(rbc::launch_set_meta(h_->meta, J.slot, {J.k & 1, J.n, J.start, 0}, js), "set_meta"))
       return -1;
-    if (!ok(hipMemcpyAsync(h_->Xring + J.slot * fs_, U_ + J.n * fs_, fs_ * 8, hipMemcpyDeviceToDevice, F_),
+    if (!ok(hipMemcpyAsync(h_->Xring + J.slot * fs_, U_ + J.n * fs_, fs_ * 8, hipMemcpyDeviceToDevice, js),
             "hipMemcpyAsync"))
       return -1;
     rbc::StepRange r;
@@ -428,15 +435,16 @@ int Pipeline::admit() {
     r.count = 1;
     r.step0 = r.step1 = 0;   // the inverse transform of the initial state only
     r.n_total = 1;
-    if (!ok(rbc::launch_step_range(fp, fw, h_->Xring, r, nullptr, 0, 0, F_), "zinv")) return -1;
-    if (!ok(hipEventRecord(ev_admit_[jn_], F_), "hipEventRecord")) return -1;
+    if (!ok(rbc::launch_step_range(fp, fw, h_->Xring, r, nullptr, 0, 0, js), "zinv")) return -1;
+    if (!ok(hipEventRecord(ev_admit_[jn_], js), "hipEventRecord")) return -1;
     ++jn_;
     did = 1;
   }
   return did;
 }
 
-// One batched step of every job in flight (mixed jobs, then FP64 jobs).
+// One batched step of every job in flight (mixed jobs on F_, FP64 jobs on
+// F64_).
 int Pipeline::fine_step() {
   if (ja_ == jn_) return 0;
   if (freal_ >= kFDepth) {
@@ -445,6 +453,11 @@ int Pipeline::fine_step() {
   }
   int jm = ja_;
   while (jm < jn_ && !jobs_[jm].f64) ++jm;
+  const bool sep = F64_ != F_ && jn_ > jm;   // FP64 jobs on their own stream this step
+  if (sep && f64real_ >= kFDepth) {
+    const int q = query(ev_step64_[f64real_ % kFDepth]);
+    if (q <= 0) return q;
+  }
   rbc::StepRange r;
   r.step0 = 1;
   r.step1 = 2;
@@ -459,20 +472,35 @@ int Pipeline::fine_step() {
   if (jn_ > jm) {
     r.slot0 = jobs_[jm].slot;
     r.count = jn_ - jm;
-    if (!ok(rbc::launch_step_range(h_->fine64, h_->wf64, h_->Xring, r, nullptr, 0, 0, F_), "fine step")) return -1;
+    if (!ok(rbc::launch_step_range(h_->fine64, h_->wf64, h_->Xring, r, nullptr, 0, 0, F64_), "fine step")) return -1;
   }
   ++t_;
-  if (want_nu_ && t_ % stride_ == 0 &&
-      !ok(rbc::launch_diag(h_->fine, h_->wf, h_->Xring, jobs_[ja_].slot, jn_ - ja_, cap_, h_->nu_f, 0, h_->meta, t_,
-                           stride_, h_->nsf, S_, F_),
-          "diagnostics"))
-    return -1;
+  if (want_nu_ && t_ % stride_ == 0) {
+    // the samples of each range on its stream, each with its own partials
+    if (!sep && !ok(rbc::launch_diag(h_->fine, h_->wf, h_->Xring, jobs_[ja_].slot, jn_ - ja_, cap_, h_->nu_f, 0,
+                                     h_->meta, t_, stride_, h_->nsf, S_, F_),
+                    "diagnostics"))
+      return -1;
+    if (sep && jm > ja_ &&
+        !ok(rbc::launch_diag(h_->fine, h_->wf, h_->Xring, jobs_[ja_].slot, jm - ja_, cap_, h_->nu_f, 0, h_->meta, t_,
+                             stride_, h_->nsf, S_, F_),
+            "diagnostics"))
+      return -1;
+    if (sep && !ok(rbc::launch_diag(h_->fine64, h_->wf64, h_->Xring, jobs_[jm].slot, jn_ - jm, cap_, h_->nu_f, 0,
+                                    h_->meta, t_, stride_, h_->nsf, S_, F64_),
+                   "diagnostics"))
+      return -1;
+  }
   while (ja_ < jn_ && jobs_[ja_].start + nf_ == t_) {
-    if (!ok(hipEventRecord(ev_done_[ja_], F_), "hipEventRecord")) return -1;
+    if (!ok(hipEventRecord(ev_done_[ja_], jobs_[ja_].f64 ? F64_ : F_), "hipEventRecord")) return -1;
     ++ja_;
   }
   if (!ok(hipEventRecord(ev_step_[freal_ % kFDepth], F_), "hipEventRecord")) return -1;
   ++freal_;
+  if (sep) {
+    if (!ok(hipEventRecord(ev_step64_[f64real_ % kFDepth], F64_), "hipEventRecord")) return -1;
+    ++f64real_;
+  }
   return 1;
 }
 
@@ -682,10 +710,11 @@ rbc_status Pipeline::run() {
   h_->stop_reason = RBC_STOP_KMAX;
   rbc_status s = setup();
   if (s != RBC_OK) return s;
-  // both streams start after the caller's work
+  // the streams start after the caller's work
   RBC_HIPCHK(h_, hipEventRecord(ev_entry_, h_->stream));
   RBC_HIPCHK(h_, hipStreamWaitEvent(F_, ev_entry_, 0));
   RBC_HIPCHK(h_, hipStreamWaitEvent(G_, ev_entry_, 0));
+  if (F64_ != F_) RBC_HIPCHK(h_, hipStreamWaitEvent(F64_, ev_entry_, 0));
   rbc_pipeline_stats& ps = h_->pstats;
   ps = rbc_pipeline_stats{};
   const auto t_start = clk::now();
@@ -731,8 +760,12 @@ rbc_status Pipeline::run() {
   stop_.store(true);
   fine.join();
   // abandoned speculative work and everything enqueued finishes here
-  const hipError_t e1 = hipStreamSynchronize(F_);
+  hipError_t e1 = hipStreamSynchronize(F_);
   const hipError_t e2 = hipStreamSynchronize(G_);
+  if (F64_ != F_) {
+    const hipError_t e3 = hipStreamSynchronize(F64_);
+    if (e1 == hipSuccess) e1 = e3;
+  }
   ps.wall_s = std::chrono::duration<double>(clk::now() - t_start).count();
   ps.host_admit_s = f_admit_s_;
   ps.host_fine_s = f_fine_s_;
