@@ -143,7 +143,7 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes);
  * The handle creates two streams of its own for the pipelined iteration
  * (three with the FP64 switch: precision RBC_MIXED and promote_fp64).
  * A process has few hardware queues (four by default), so live handles
- * beyond the one iterating can leave its two streams on a shared queue,
+ * beyond the one iterating can leave its streams on a shared queue,
  * where they no longer overlap: destroy handles that are done.
  * Environment, read here (measurement aids): RBC_MODE_TILE = 2, 4, 6 or 8
  * sets the modes per block of the per-mode kernel; RBC_COARSE_PRIO = 0
