@@ -75,10 +75,15 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.T_bot = p->T_bot; g.T_top = p->T_top;
   g.flux = (p->bc_T == RBC_BC_FLUX);
   // The coarse sweep is serial and runs beside the batched fine launches on
-  // the same compute units: its waves take the SIMD issue slots first.
-  // RBC_COARSE_PRIO=0 turns this off (for measurement).
+  // the same compute units: its waves take the SIMD issue slots first, and
+  // its launches stay on one XCD, so that what one launch writes and the
+  // next reads (and the grid's tables) stay in that XCD's L2.
+  // RBC_COARSE_PRIO=0 and RBC_COARSE_ONE_XCD=0 turn these off (for
+  // measurement).
   g.urgent = coarse;
   if (const char* e = std::getenv("RBC_COARSE_PRIO")) g.urgent = coarse && std::atoi(e) != 0;
+  g.one_xcd = coarse;
+  if (const char* e = std::getenv("RBC_COARSE_ONE_XCD")) g.one_xcd = coarse && std::atoi(e) != 0;
   g.scheme = coarse ? p->scheme_c : p->scheme_f;
   g.mixed = (p->precision == RBC_MIXED);
   // modes per block of the per-mode kernel (2, 4, 6 or 8); RBC_MODE_TILE overrides

@@ -27,7 +27,12 @@ constexpr int kDiag = 6;          // diagnostic record: Nu_V, Nu_b, Nu_t, KE, ep
 constexpr int kDiagAvg = 9;       // time averages: Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, epsilon_U, P, |P-eps|/P
 // Fourier modes per block of the diagnostics kernel (Nz coefficients each).
 __host__ __device__ inline int diag_modes(int Nz) { return Nz >= 512 ? 1 : 512 / Nz; }
-constexpr int kBlock = 256;       // threads per block of the per-mode kernels
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;           // XCDs of the device; workgroup b runs on XCD b mod kXcds
+
+// Workgroups to launch for nwork work blocks (GridDev::one_xcd: kXcds per
+// work block, of which the one on XCD 0 works and the others exit at once).
+inline int xcd_grid(int one_xcd, int nwork) { return one_xcd ? nwork * kXcds : nwork; }       // threads per block of the per-mode kernels
 
 // Per-row entries of the stored bordered band factorisations (rbc_plan.cpp).
 constexpr int kFacT = 4;          // lm, 1/u_ii, u_i,i+1, v      (bordered tridiagonal)
@@ -55,6 +60,7 @@ struct GridDev {
   double bcT[2];                  // m = 0 temperature wall values per parity (wall rows of the plan)
   int fluxT;                      // 1: temperature wall rows are slopes (fixed flux)
   int urgent;                     // 1: waves run at raised SIMD issue priority (coarse grid)
+  int one_xcd;                    // 1: x-pass / per-mode launches run on XCD 0 only (coarse grid)
   const double* bS10;             // [2][n][3]  S1S0 rows, half offsets 0..2
   const double* bD2;              // [2][n]     D2 rows, half offset 1
   const double* bA;               // [2][n][3]  S3S2D2 rows, half offsets 1..3
@@ -76,6 +82,7 @@ struct GridPlan {
   double T_bot = 1, T_top = 0;
   bool flux = false;              // fixed-flux temperature walls (Eq. 5)
   bool urgent = false;            // coarse grid: the serial sweep is the critical path
+  bool one_xcd = false;           // see GridDev::one_xcd
   int scheme = 4;
   Tableau tab;
   int MT = 8;

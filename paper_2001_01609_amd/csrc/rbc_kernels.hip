@@ -40,6 +40,15 @@ __device__ __forceinline__ Cx<Real> cmul(Cx<Real> a, Cx<Real> b) {
 template <typename Real>
 __device__ __forceinline__ Cx<Real> cadd(Cx<Real> a, Cx<Real> b) { return {a.x + b.x, a.y + b.y}; }
 
+// Work block of this workgroup, or -1: the workgroup exits at once.  With
+// one_xcd (GridDev::one_xcd) the launch has kXcds workgroups per work block
+// and only those on XCD 0 work.
+__device__ __forceinline__ int work_block(int one_xcd) {
+  const int b = blockIdx.x;
+  if (!one_xcd) return b;
+  return (b % kXcds) ? -1 : b / kXcds;
+}
+
 // Batch position b -> slot of the state ring (slots slot0, slot0 + 1, ... mod
 // cap).  A plain batch is the ring read from slot 0 without wrapping.
 __device__ __forceinline__ int ring_slot(int b, int slot0, int cap) {
@@ -205,7 +214,9 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
   extern __shared__ __align__(16) unsigned char smem[];
   const int Pz = g.Pz, Mx = g.Mx, MT = g.MT, ntile = g.ntile;
   const int ngrp = Pz / RB;
-  const int b = blockIdx.x / ngrp, jg = blockIdx.x - b * ngrp;
+  const int bid = work_block(g.one_xcd);
+  if (bid < 0) return;
+  const int b = bid / ngrp, jg = bid - b * ngrp;
   const int s = ring_slot(b, slot0, cap);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = jg * RB + wv;
@@ -652,7 +663,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   extern __shared__ __align__(16) unsigned char smem[];
   const int Mx = g.Mx;
   const int ntile = g.ntile;   // ceil(Mx / MT)
-  const int b = blockIdx.x / ntile, tile = blockIdx.x - b * ntile;
+  const int bid = work_block(g.one_xcd);
+  if (bid < 0) return;
+  const int b = bid / ntile, tile = bid - b * ntile;
   const int s = ring_slot(b, a.slot0, a.cap);
   const int m0 = tile * MT;
   const int st = g.state;
@@ -1476,7 +1489,8 @@ hipError_t run_stage_t(const GridPlan& g, Work& w, const StageArgs& a, double* X
   const int ntile = (d.Mx + MT - 1) / MT;
   constexpr bool pre = MT <= 2 && NZ <= 64;   // as in the kernel
   const size_t lds = stage_lds<NZ, MT>(sizeof(Real), d.facT_stride, d.facP_stride, pre).total;
-  hipLaunchKernelGGL((stage_kernel<Real, NZ, MT>), dim3(n_slices * ntile), dim3(kBlock), lds, st, d, a,
+  hipLaunchKernelGGL((stage_kernel<Real, NZ, MT>), dim3(xcd_grid(d.one_xcd, n_slices * ntile)), dim3(kBlock), lds, st,
+                     d, a,
                      (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q, Eout);
   return hipGetLastError();
 }
@@ -1522,12 +1536,12 @@ hipError_t run_xpass_t(const GridPlan& g, Work& w, int slot0, int n_slices, hipS
   // with several rows per block: one row per block there
   if (RB > 1 && n_slices * (d.Pz / RB) < 256) {
     const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, 1>() * size_t(PX);
-    hipLaunchKernelGGL((xpass_kernel<Real, PX, 1>), dim3(n_slices * d.Pz), dim3(64), lds, st, d, (const Real*)w.Q,
-                       (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
+    hipLaunchKernelGGL((xpass_kernel<Real, PX, 1>), dim3(xcd_grid(d.one_xcd, n_slices * d.Pz)), dim3(64), lds, st,
+                       d, (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
   } else {
     const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, RB>() * size_t(PX) * RB;
-    hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(n_slices * (d.Pz / RB)), dim3(64 * RB), lds, st, d,
-                       (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
+    hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(xcd_grid(d.one_xcd, n_slices * (d.Pz / RB))),
+                       dim3(64 * RB), lds, st, d, (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
   }
   return hipGetLastError();
 }

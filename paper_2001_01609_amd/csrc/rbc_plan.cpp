@@ -413,6 +413,7 @@ hipError_t upload_plan(GridPlan& g) {
   d.bcT[1] = g.flux ? -0.5 * g.Lz : 0.5 * (g.T_top - g.T_bot);
   d.fluxT = g.flux ? 1 : 0;
   d.urgent = g.urgent ? 1 : 0;
+  d.one_xcd = g.one_xcd ? 1 : 0;
   d.bS10 = reinterpret_cast<const double*>(base + offs[0]);
   d.bD2 = reinterpret_cast<const double*>(base + offs[1]);
   d.bA = reinterpret_cast<const double*>(base + offs[2]);

@@ -141,16 +141,18 @@ def test_iterate_history(pipelined):
     assert not np.array_equal(H[1], H[2])
 
 
-def test_coarse_wave_priority_changes_no_result(monkeypatch):
-    """The coarse-grid kernels raise their wave priority (issue order on the
-    SIMDs only): the same pipelined run with it turned off gives the same
-    states, defects and Nu histories bit for bit."""
+@pytest.mark.parametrize("env", ["RBC_COARSE_PRIO", "RBC_COARSE_ONE_XCD"])
+def test_coarse_launch_placement_changes_no_result(env, monkeypatch):
+    """The coarse-grid kernels raise their wave priority and run on one XCD
+    (issue order and placement only): the same pipelined run with either
+    turned off gives the same states, defects and Nu histories bit for
+    bit."""
     c = CASES["mixed_promote"]
-    case("coarse wave priority on/off")
+    case(f"coarse launch placement: {env} on/off")
     g = O.Grid(3e3, 1.0, 2.0, 1.0, c["p"]["Nx"], c["p"]["Nz"], c["p"]["dt"])
     U0 = O.initial_state(g, I.gaussian_noise(35, g.Nx, g.Nz), 0.3).pack()
     a = run(params(**c["p"]), 1, U0, c["k_max"], c["tol"], True)
-    monkeypatch.setenv("RBC_COARSE_PRIO", "0")
+    monkeypatch.setenv(env, "0")
     b = run(params(**c["p"]), 1, U0, c["k_max"], c["tol"], True)
     assert a[0] == b[0] and a[1] == b[1] and a[4] == b[4]
     assert np.array_equal(a[2], b[2])
