@@ -148,7 +148,8 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes);
  * Environment, read here (measurement aids): RBC_MODE_TILE = 2, 4, 6 or 8
  * sets the modes per block of the per-mode kernel; RBC_COARSE_PRIO = 0
  * keeps the coarse-grid kernels at the default wave priority;
- * RBC_COARSE_ONE_XCD = 0 spreads their launches over all XCDs. */
+ * RBC_COARSE_ONE_XCD = 0 spreads the launches of a mixed coarse plan over
+ * all XCDs. */
 rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out);
 rbc_status rbc_destroy(rbc_handle h);
 

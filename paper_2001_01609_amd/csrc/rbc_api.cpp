@@ -74,18 +74,19 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.dt = dt;
   g.T_bot = p->T_bot; g.T_top = p->T_top;
   g.flux = (p->bc_T == RBC_BC_FLUX);
-  // The coarse sweep is serial and runs beside the batched fine launches on
-  // the same compute units: its waves take the SIMD issue slots first, and
-  // its launches stay on one XCD, so that what one launch writes and the
-  // next reads (and the grid's tables) stay in that XCD's L2.
-  // RBC_COARSE_PRIO=0 and RBC_COARSE_ONE_XCD=0 turn these off (for
-  // measurement).
-  g.urgent = coarse;
-  if (const char* e = std::getenv("RBC_COARSE_PRIO")) g.urgent = coarse && std::atoi(e) != 0;
-  g.one_xcd = coarse;
-  if (const char* e = std::getenv("RBC_COARSE_ONE_XCD")) g.one_xcd = coarse && std::atoi(e) != 0;
   g.scheme = coarse ? p->scheme_c : p->scheme_f;
   g.mixed = (p->precision == RBC_MIXED);
+  // The coarse sweep is serial and runs beside the batched fine launches on
+  // the same compute units: its waves take the SIMD issue slots first, and
+  // the launches of a mixed coarse plan stay on one XCD, so that what one
+  // launch writes and the next reads (and the grid's tables) stay in that
+  // XCD's L2.  (FP64 coarse blocks beside FP64 fine blocks lose more to the
+  // fewer compute units than they gain.)  RBC_COARSE_PRIO=0 and
+  // RBC_COARSE_ONE_XCD=0 turn these off (for measurement).
+  g.urgent = coarse;
+  if (const char* e = std::getenv("RBC_COARSE_PRIO")) g.urgent = coarse && std::atoi(e) != 0;
+  g.one_xcd = coarse && g.mixed;
+  if (const char* e = std::getenv("RBC_COARSE_ONE_XCD")) g.one_xcd = g.one_xcd && std::atoi(e) != 0;
   // modes per block of the per-mode kernel (2, 4, 6 or 8); RBC_MODE_TILE overrides
   // (the single-slice coarse grid and single-run fine batches are latency-bound:
   // small tiles, more blocks)
@@ -230,6 +231,7 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
     setup_grid(h->fine64, p, false, dtf);
     setup_grid(h->coarse64, p, true, dtc);
     h->fine64.mixed = h->coarse64.mixed = false;
+    h->coarse64.one_xcd = false;
     e = rbc::build_plan(h->fine64);
     if (e.empty()) e = rbc::build_plan(h->coarse64);
   }
