@@ -1,0 +1,48 @@
+"""Host-side logic of bench.py (no GPU): the byte model behind the roofline
+figure, the one-GPU guard, the time averages of section 2.2 and the
+traffic summary lookup."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_stage_kernel_byte_model():
+    # mixed precision (4-byte bulk data), ARS443 (four stages): the per-DOF
+    # traffic of one fine step, term by term
+    reads = 4 * 12 + 4 * 16 + (0 + 1 + 2 + 3) * 8 + (0 + 1 + 2 + 3) * 16
+    writes = 3 * (8 + 16) + 16 + 4 * 36
+    assert bench.stage_kernel_bytes_per_dof_step(4, 4) == reads + writes == 488
+    # FP64 doubles the bulk terms only
+    assert bench.stage_kernel_bytes_per_dof_step(4, 8) == 488 + 4 * 12 + 6 * 8 + 3 * 8 + 4 * 36
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_time_averages_follow_section_2_2():
+    # records (Nu_V, Nu_b, Nu_t, KE, eps_U, P)
+    rec = np.array([[2.0, 2.2, 1.8, 0.5, 0.010, 0.012],
+                    [4.0, 3.8, 4.2, 2.0, 0.030, 0.028]])
+    visc = 1e-3
+    out = bench.diag_time_averages(rec, visc)
+    nv, nb, nt = 3.0, 3.0, 3.0
+    assert np.allclose(out[:3], [nv, nb, nt])
+    assert out[3] == 0.0                                   # Nu_int (Eq. 11)
+    assert np.isclose(out[4], 1.25)                        # KE
+    assert np.isclose(out[5], (1.0 + 2.0) / 2 / visc)      # Re = <sqrt(2 KE)> / nu
+    assert np.isclose(out[8], abs(0.020 - 0.020) / 0.020)  # |P - eps_U| / P (Eq. 12)
+
+
+def test_traffic_summary_is_ignored_for_another_workload():
+    assert bench.measured_traffic("no_such_workload") is None

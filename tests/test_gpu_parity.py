@@ -576,3 +576,53 @@ def test_parareal_fixed_flux_matches_oracle_iterates():
     for nn in range(p.n_slices + 1):
         assert rel(got[nn], ref.U[nn]) < FP64_TOL, nn
     assert np.allclose(defects, ref.defects, rtol=1e-8, atol=1e-14)
+
+
+def test_c1_parareal_to_finite_termination_matches_stored_oracle_samples():
+    """The 64x32, 4-slice FP64 workload (Ra 1e4, ARS222, t in [0, 10], the
+    coarse propagator on the same grid at ten times the step), Parareal to
+    k = 4: the defects, and for every iterate and slice boundary the L2 norm
+    and 16 coefficients, against the oracle's (tests/golden/c1_parareal.json,
+    written by tests/golden/make_c1_parareal.py from the oracle alone; the
+    oracle needs minutes for this run), each block of the state (psi, T for
+    m >= 1, T for m = 0) relative to its own norm.  Bound: the FP64 bar of 1e-11 of
+    the slice norm; over the four slices the oracle amplifies a
+    rounding-level perturbation of the initial state at most ~6 times.  The
+    coarse propagator shares the fine grid, so after the first iteration
+    (4.5e-10) the defects are rounding noise (~1e-14) on both sides."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_parareal.json")) as f:
+        gold = json.load(f)
+    w = I.C1
+    p = R().params_from_workload(w)
+    S = p.n_slices
+    case(f"{w.name}: Parareal to k = {S} vs stored oracle samples")
+    g = grid(p)
+    U0 = O.initial_state(g, I.gaussian_noise(w.seed, g.Nx, g.Nz), w.noise_amp).pack()
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        hist = torch.zeros((S + 1) * (S + 1) * n, dtype=torch.float64, device=dev())
+        R().rbc_set_iterate_history(h, hist, S)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev())
+        U[:n] = to_dev(U0)
+        st, kd, defects, _ = R().parareal_iterate(h, U, S, 0.0)
+        H = hist.view(S + 1, S + 1, n).cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    assert kd == gold["k_done"] == S
+    ref_d = np.array(gold["defects"])
+    # a difference of two states 4.5e-10 apart: relative accuracy ~1e-15 / 4.5e-10
+    assert abs(defects[0] - ref_d[0]) <= 1e-4 * ref_d[0], (defects, ref_d)
+    assert np.all(np.asarray(defects[1:]) < 1e-12) and np.all(ref_d[1:] < 1e-12), (defects, ref_d)
+    tol = FP64_TOL
+    for name, blk in gold["blocks"].items():
+        a, b = blk["range"]
+        pos = np.array(blk["positions"])
+        for k in range(S + 1):
+            for nn in range(S + 1):
+                ref_norm = blk["norms"][k][nn]
+                got = H[k][nn]
+                assert abs(np.linalg.norm(got[a:b]) - ref_norm) <= tol * ref_norm, (name, k, nn)
+                err = np.max(np.abs(got[pos] - np.array(blk["samples"][k][nn])))
+                assert err <= tol * ref_norm, (name, k, nn, err / ref_norm)
