@@ -109,9 +109,19 @@ __device__ __forceinline__ void dft_small(const Cx<Real>* a, Real sign, Cx<Real>
   }
 }
 
+// Orders the LDS accesses of one wavefront's lanes around this point.  An
+// x-pass row lives in LDS that only its own wavefront touches, and the LDS
+// operations of a wavefront complete in issue order, so exchanging values
+// between its lanes needs no workgroup barrier, only this compiler fence.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // In-place Stockham radix-R pass (Bainville's autosort form) over CNT
 // signals of length N (stride N) by one 64-lane wavefront: every lane first
-// gathers the inputs of its butterflies into registers, the block syncs,
+// gathers the inputs of its butterflies into registers, the wave syncs,
 // then writes out[j + q P] = DFT_R over in[i + r N/R] twiddled by
 // exp(sign 2 pi i r k / (P R)), k = i mod P, j = (i - k) R + k.  The radix
 // plan is 8, ..., 8, (4 or 2), 3, so P is a power of two in every pass and
@@ -146,7 +156,7 @@ __device__ __forceinline__ void stockham_pass(Cx<Real>* x, const Cx<Real>* __res
         }
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = lane + 64 * b;
@@ -160,7 +170,7 @@ __device__ __forceinline__ void stockham_pass(Cx<Real>* x, const Cx<Real>* __res
       for (int q = 0; q < R; ++q) x[c * N + j + q * P] = y[q];
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
 // Radix plan for N = 3 * 2^q: eights, then a four or a two, then the three.
@@ -252,7 +262,7 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
   Real uw = 0;
   if constexpr (NA == 3) {
     pack(0, 3, 0);
-    __syncthreads();
+    wave_sync();
     fft_wave<Real, PX, 1, 3>(A, tw, Real(1));
     for (int t = lane; t < PX; t += 64) {
       const Cx<Real> v1 = A[t], v2 = A[PX + t], v3 = A[2 * PX + t];
@@ -264,7 +274,7 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
     constexpr int NT = (PX + 63) / 64;
     Real nw[NT];
     pack(0, 2, 0);
-    __syncthreads();
+    wave_sync();
     fft_wave<Real, PX, 1, 2>(A, tw, Real(1));
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -276,9 +286,9 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
         uw += v1.x * v1.y;
       }
     }
-    __syncthreads();
+    wave_sync();
     pack(2, 3, 1);   // (T_x, T_z) into the second spectrum
-    __syncthreads();
+    wave_sync();
     fft_wave<Real, PX, 1, 1>(A + PX, tw, Real(1));
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -291,7 +301,7 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
   }
   uw = wave_sum(uw);
   if (lane == 0) qbar[size_t(s) * Pz + j] = uw / Real(PX);
-  __syncthreads();
+  wave_sync();
   fft_wave<Real, PX, 1, 1>(A, tw, Real(-1));
   const Real inv2 = Real(0.5) / Real(PX);
   Cx<Real>* out = reinterpret_cast<Cx<Real>*>(Nh) + size_t(s) * 2 * ntile * tq + size_t(j) * MT;
