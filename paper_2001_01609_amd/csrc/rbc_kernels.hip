@@ -849,6 +849,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       // two-mode tiles: each item split over JS lanes that take every JS-th
       // Gauss point, summed by shuffles
     constexpr int JS = 4;
+    // Gauss points per lane; the latency variant issues all their map loads
+    // at once
+    constexpr int NJ = (PH + JS - 1) / JS, UB = kPre ? NJ : 4;
     const int nitems = ((m0 == 0) ? 3 : 2) * NZ;
     for (int e = tid; e < nitems * JS; e += kBlock) {
       const int lane = e & (JS - 1), item = e / JS;
@@ -860,15 +863,20 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (rr < NZ - 2) {
           const Real* w = W + (size_t(2) * NZ + rr) * PH;
           const Real sg = (rr & 1) ? Real(1) : Real(-1);
-#pragma unroll 4
-          for (int j = lane; j < PH; j += JS) acc[0] += w[j] * (sq[j] + sg * sq[PZ - 1 - j]);
+#pragma unroll UB
+          for (int i = 0; i < NJ; ++i) {
+            const int j = lane + i * JS;
+            if (j < PH) acc[0] += w[j] * (sq[j] + sg * sq[PZ - 1 - j]);
+          }
         }
       } else if (rr < ((f == 0) ? NZ - 4 : NZ - 2)) {
         const Real* w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
         const Real* src = sN + (f == 0 ? 0 : PZ * 2 * MT);
         const Real sg = (rr & 1) ? Real(-1) : Real(1);
-#pragma unroll 4
-        for (int j = lane; j < PH; j += JS) {
+#pragma unroll UB
+        for (int i = 0; i < NJ; ++i) {
+          const int j = lane + i * JS;
+          if (j >= PH) break;
           const Real wv = w[j];
           const Real* a0 = src + j * 2 * MT;
           const Real* a1 = src + (PZ - 1 - j) * 2 * MT;
@@ -1116,8 +1124,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         for (int q = 0; q < 4; ++q) acc[pp][q] = Real(0);
       const Real* w = Wi + size_t(j) * NZ;
       constexpr size_t QS = size_t(PH) * NZ;
+      constexpr int UG = kPre ? 8 : 4;   // coefficient pairs per round of map loads
       if (f == 0) {
-#pragma unroll 4
+#pragma unroll UG
         for (int nn = 0; nn < NZ; nn += 2) {
 #pragma unroll
           for (int pp = 0; pp < 2; ++pp) {
@@ -1127,7 +1136,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           }
         }
       } else {
-#pragma unroll 4
+#pragma unroll UG
         for (int nn = 0; nn < NZ; nn += 2) {
 #pragma unroll
           for (int pp = 0; pp < 2; ++pp) {
