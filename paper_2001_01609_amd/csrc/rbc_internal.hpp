@@ -27,12 +27,12 @@ constexpr int kDiag = 6;          // diagnostic record: Nu_V, Nu_b, Nu_t, KE, ep
 constexpr int kDiagAvg = 9;       // time averages: Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, epsilon_U, P, |P-eps|/P
 // Fourier modes per block of the diagnostics kernel (Nz coefficients each).
 __host__ __device__ inline int diag_modes(int Nz) { return Nz >= 512 ? 1 : 512 / Nz; }
-constexpr int kBlock = 256;
-constexpr int kXcds = 8;           // XCDs of the device; workgroup b runs on XCD b mod kXcds
+constexpr int kBlock = 256;       // threads per block of the per-mode kernels
+constexpr int kXcds = 8;          // XCDs of the device; workgroup b runs on XCD b mod kXcds
 
 // Workgroups to launch for nwork work blocks (GridDev::one_xcd: kXcds per
 // work block, of which the one on XCD 0 works and the others exit at once).
-inline int xcd_grid(int one_xcd, int nwork) { return one_xcd ? nwork * kXcds : nwork; }       // threads per block of the per-mode kernels
+inline int xcd_grid(int one_xcd, int nwork) { return one_xcd ? nwork * kXcds : nwork; }
 
 // Per-row entries of the stored bordered band factorisations (rbc_plan.cpp).
 constexpr int kFacT = 4;          // lm, 1/u_ii, u_i,i+1, v      (bordered tridiagonal)
