@@ -5,10 +5,10 @@
  * Convection").
  *
  * The library advances the Oberbeck-Boussinesq equations (section 2.1,
- * Eqs. 1-4) on a Fourier(x) x Chebyshev(z) grid (section 3.2) with
+ * Eqs. 3-7) on a Fourier(x) x Chebyshev(z) grid (section 3.2) with
  * implicit-explicit Runge-Kutta steps (sections 3.2 and 3.6), on every
  * Parareal time slice at once, and runs the Parareal iteration (section
- * 3.1, Eq. 13) around it on the device.
+ * 3.1, Eq. 19) around it on the device.
  *
  * Conventions shared by every call:
  *  - Every function returns rbc_status; nothing throws across the ABI.
@@ -16,7 +16,7 @@
  *    warnings with valid outputs.  rbc_last_error() describes the last one.
  *  - Units are free-fall units on z in [0, Lz]: viscosity sqrt(Pr/Ra),
  *    thermal diffusivity 1/sqrt(Ra Pr), buoyancy coefficient 1.  The
- *    paper writes Eqs. 1-3 in thermal-diffusion units on z in [-1/2, 1/2];
+ *    paper writes Eqs. 3-5 in thermal-diffusion units on z in [-1/2, 1/2];
  *    the two differ only by the time and velocity scales.
  *  - A state is one time level of one run, FP64, laid out as
  *        [field][m][re, im][n]
@@ -61,16 +61,16 @@ typedef enum {
 typedef enum { RBC_FP64 = 0, RBC_MIXED = 1 } rbc_precision;
 
 /* Diagnostic record of one state (section 2.2), RBC_DIAG doubles:
- *   Nu_V (Eq. 8), Nu_b (Eq. 9), Nu_t (Eq. 10), each divided by the
+ *   Nu_V (Eq. 9), Nu_b (Eq. 10), Nu_t (Eq. 11), each divided by the
  *   conductive flux dT/Lz of the current mean temperature drop dT = <T>(z=0)
  *   - <T>(z=Lz) (dT = 1 for fixed temperatures; Nu = 1/dT for fixed flux),
  *   KE = <u^2 + w^2>/2,
  *   epsilon_U = nu <|grad u|^2> (viscous dissipation), P = <w T> (buoyancy
  *   production), all volume means in free-fall units, exact for the
  *   discrete fields.  Time averages, RBC_DIAG_AVG doubles:
- *   Nu_V, Nu_b, Nu_t, Nu_int (Eq. 11, on the averaged Nusselt numbers), KE,
+ *   Nu_V, Nu_b, Nu_t, Nu_int (Eq. 13, on the averaged Nusselt numbers), KE,
  *   Re (mean of <u^2 + w^2>^(1/2) over the viscosity), epsilon_U, P,
- *   |P - epsilon_U| / P (the balance check of Eq. 12). */
+ *   |P - epsilon_U| / P (the balance check of Eq. 15). */
 #define RBC_DIAG 6
 #define RBC_DIAG_AVG 9
 
@@ -82,8 +82,8 @@ typedef enum {
   RBC_STOP_EXACT = 3        /* k = n_slices: the serial fine solution           */
 } rbc_stop;
 typedef enum { RBC_ARS222 = 2, RBC_ARS443 = 4 } rbc_scheme;
-/* Temperature walls: fixed temperatures T_bot, T_top (Eq. 4) or fixed flux
- * dT/dz = -1 at both walls (Eq. 5; Ra is then the flux Rayleigh number Ra_f,
+/* Temperature walls: fixed temperatures T_bot, T_top (Eq. 6) or fixed flux
+ * dT/dz = -1 at both walls (Eq. 7; Ra is then the flux Rayleigh number Ra_f,
  * T_top is unused and the initial profile is T_bot - z).  The velocity is
  * no-slip in both. */
 typedef enum { RBC_BC_TEMPERATURE = 0, RBC_BC_FLUX = 1 } rbc_bc;
@@ -107,7 +107,7 @@ typedef struct {
                               solves, correction, defect and Nusselt       */
   int32_t nu_stride;       /* sample Nu every nu_stride fine steps; 0 = off */
   double nu_t_start;       /* start of the Nu time-average window           */
-  double T_bot, T_top;     /* wall temperatures at z = 0 and z = Lz (Eq. 4) */
+  double T_bot, T_top;     /* wall temperatures at z = 0 and z = Lz (Eq. 6) */
   int32_t promote_fp64;    /* RBC_MIXED only: 1 = before parareal_iterate's
                               defect meets the FP32 rounding floor (near
                               1e-7), switch to all-FP64 propagators: after
@@ -172,7 +172,7 @@ rbc_status rbc_steps_per_slice(rbc_handle h, int32_t coarse, int32_t* n_steps, d
 rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double noise_amp, double* U0_dev);
 
 /* The fine propagator F on a batch of slices (the data-parallel half of
- * Eq. 13): n_steps IMEX steps of the fine grid on each of n_slices
+ * Eq. 19): n_steps IMEX steps of the fine grid on each of n_slices
  * independent states.  U_in and U_out are [n_slices][state] (they may be
  * the same pointer).  If nu_samples_dev is not NULL and nu_stride > 0 it
  * receives [n_slices][n_steps / nu_stride][RBC_DIAG] diagnostic records
@@ -180,7 +180,7 @@ rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double noise_amp, double*
 rbc_status rbc_fine_step_batch(rbc_handle h, const double* U_in_dev, double* U_out_dev,
                                int32_t n_slices, int32_t n_steps, double* nu_samples_dev);
 
-/* The serial coarse sweep of Eq. 13 (G = prolong o coarse steps o restrict,
+/* The serial coarse sweep of Eq. 19 (G = prolong o coarse steps o restrict,
  * restriction = keep the first Nx_c/2 modes and Nz_c coefficients,
  * prolongation = zero-pad).  U_dev is [n_slices + 1][state];
  * G_dev is [n_slices][coarse state].
@@ -195,7 +195,7 @@ rbc_status rbc_coarse_sweep(rbc_handle h, int32_t mode, int32_t first_slice,
                             double* U_dev, const double* F_dev, double* G_dev,
                             double* defect_host);
 
-/* Parareal (section 3.1, Eq. 13) on the device.  U_dev is [n_slices+1][state];
+/* Parareal (section 3.1, Eq. 19) on the device.  U_dev is [n_slices+1][state];
  * on entry U_dev[0] is the initial state, on return U_dev[n] = U_n^K.
  * Iteration 0 is the coarse prediction.  Iteration k runs F on slices
  * k-1..S-1 (the earlier ones are already exact), then the coarse
@@ -253,7 +253,7 @@ typedef struct {
 } rbc_pipeline_stats;
 rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out);
 
-/* Nusselt numbers of section 2.2 for n_states fine states (Eqs. 8-10):
+/* Nusselt numbers of section 2.2 for n_states fine states (Eqs. 9-11):
  * nu_host[i] = (Nu_V, Nu_b, Nu_t).  Nu_b, Nu_t: -dT/dz of the horizontal
  * mean at z = 0 and z = Lz.  Nu_V: volume mean of -dT/dz + sqrt(Ra Pr) w T,
  * integrated exactly for the discrete fields.  Synchronises. */

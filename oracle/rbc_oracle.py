@@ -6,8 +6,8 @@ shares no code with it.
 
 What it computes (each function names the part of the paper it follows):
 
-* the Oberbeck-Boussinesq equations of section 2.1 (Eqs. 1-3) with the
-  no-slip walls of fixed temperature (Eq. 4) or fixed flux (Eq. 5, with
+* the Oberbeck-Boussinesq equations of section 2.1 (Eqs. 3-5) with the
+  no-slip walls of fixed temperature (Eq. 6) or fixed flux (Eq. 7, with
   the flux Rayleigh number Ra_f in place of Ra), written in free-fall units on
   z in [0, Lz] (the reading used for the workloads: viscosity sqrt(Pr/Ra),
   diffusivity 1/sqrt(Ra Pr), buoyancy coefficient 1), in the
@@ -18,11 +18,11 @@ What it computes (each function names the part of the paper it follows):
   named in sections 3.2 and 3.6 (ARS(2,2,2) and ARS(4,4,3)): diffusion and
   buoyancy implicit, advection explicit; each stage solve is a dense LU
   with partial pivoting of the tau-modified ultraspherical system;
-* the Nusselt numbers of section 2.2 (Eqs. 8-10) and the other quantities
+* the Nusselt numbers of section 2.2 (Eqs. 9-11) and the other quantities
   of its consistency checks: the Reynolds number from the RMS velocity, the
-  spread Nu_int of the three Nusselt numbers (Eq. 11), and the buoyancy
-  production P against the viscous dissipation epsilon_U (Eq. 12);
-* the Parareal iteration of section 3.1 (Eq. 13), serially, with a coarse
+  spread Nu_int of the three Nusselt numbers (Eq. 13), and the buoyancy
+  production P against the viscous dissipation epsilon_U (Eq. 15);
+* the Parareal iteration of section 3.1 (Eq. 19), serially, with a coarse
   propagator built by spatial coarsening and a larger step (section 3.6).
 
 Readings where the paper is silent are listed in the design notes; the
@@ -154,8 +154,8 @@ class Grid:
     Ra, Pr: Rayleigh and Prandtl numbers (section 2.1); Lx, Lz: box size
     (aspect ratio 2 in the paper); Nx, Nz: collocation points (section 3.2);
     dt: time step; scheme: 2 or 4 (see ars_tableau).  flux: fixed-flux
-    walls dT/dz = -1 (Eq. 5; Ra is then the flux Rayleigh number Ra_f)
-    instead of the fixed temperatures T_bot, T_top (Eq. 4).
+    walls dT/dz = -1 (Eq. 7; Ra is then the flux Rayleigh number Ra_f)
+    instead of the fixed temperatures T_bot, T_top (Eq. 6).
     """
     Ra: float
     Pr: float
@@ -165,9 +165,9 @@ class Grid:
     Nz: int
     dt: float
     scheme: int = 4
-    T_bot: float = 1.0   # temperature at z = 0 (Eq. 4)
-    T_top: float = 0.0   # temperature at z = Lz (Eq. 4)
-    flux: bool = False   # fixed-flux walls (Eq. 5)
+    T_bot: float = 1.0   # temperature at z = 0 (Eq. 6)
+    T_top: float = 0.0   # temperature at z = Lz (Eq. 6)
+    flux: bool = False   # fixed-flux walls (Eq. 7)
 
     def __post_init__(self):
         if self.Nx % 4 or self.Nz % 2:
@@ -281,8 +281,8 @@ def conduction_state(g: Grid) -> State:
 class Operators:
     """M (mass), L (implicit linear part) and B (buoyancy coupling) per mode.
 
-    Temperature (Eq. 3):   M = S1 S0,                L = kappa (D2 - k^2 S1 S0)
-    Vorticity (curl of Eq. 1), streamfunction psi, m >= 1:
+    Temperature (Eq. 5):   M = S1 S0,                L = kappa (D2 - k^2 S1 S0)
+    Vorticity (curl of Eq. 3), streamfunction psi, m >= 1:
         M = S3 S2 (D2 - k^2 S1 S0)                    (Laplacian of psi)
         L = nu (D4 - 2 k^2 S3 S2 D2 + k^4 S3 S2 S1 S0) (nu times bi-Laplacian)
         B = -i k S3 S2 S1 S0 acting on T               (buoyancy, -dT/dx)
@@ -505,10 +505,10 @@ class Stepper:
 
 
 def nusselt(g: Grid, X: State):
-    """(Nu_V, Nu_b, Nu_t) of Eqs. 8-10, in free-fall units, each divided by
+    """(Nu_V, Nu_b, Nu_t) of Eqs. 9-11, in free-fall units, each divided by
     the conductive flux of the current mean temperature drop, dT / Lz with
-    dT = <T>_H(z=0) - <T>_H(z=Lz) (1 for the fixed temperatures of Eq. 4;
-    for the fixed flux of Eq. 5 this is the Nu = 1 / dT of that case).
+    dT = <T>_H(z=0) - <T>_H(z=Lz) (1 for the fixed temperatures of Eq. 6;
+    for the fixed flux of Eq. 7 this is the Nu = 1 / dT of that case).
 
     Nu_b, Nu_t: -dT/dz of the horizontal mean at z = 0 and z = Lz (exact
     endpoint derivatives of the Chebyshev series).
@@ -611,7 +611,7 @@ def time_averages(g: Grid, samples: np.ndarray) -> np.ndarray:
     epsilon_U, P): (Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, epsilon_U, P,
     |P - epsilon_U| / P).  Re is the time average of the RMS velocity
     <u^2 + w^2>^(1/2) over the viscosity (free-fall velocity, height 1);
-    Nu_int is Eq. 11 on the averaged Nusselt numbers."""
+    Nu_int is Eq. 13 on the averaged Nusselt numbers."""
     s = np.asarray(samples, dtype=np.float64).reshape(-1, 6)
     nv, nb, nt, ke, eps, P = s.mean(axis=0)
     re = np.mean(np.sqrt(2.0 * s[:, 3])) / g.nu
@@ -640,7 +640,7 @@ def prolong(X: State, Mx: int, Nz: int) -> State:
 
 
 # --------------------------------------------------------------------------
-# Parareal (section 3.1, Eq. 13), serial.
+# Parareal (section 3.1, Eq. 19), serial.
 # --------------------------------------------------------------------------
 
 
@@ -665,7 +665,7 @@ def parareal(U0: np.ndarray, n_slices: int, F: Callable, G: Callable,
     """Parareal on packed state vectors.
 
     k = 0: U_(n+1)^0 = G(U_n^0).  Iteration k >= 1:
-        U_(n+1)^k = G(U_n^k) + F(U_n^(k-1)) - G(U_n^(k-1))      (Eq. 13).
+        U_(n+1)^k = G(U_n^k) + F(U_n^(k-1)) - G(U_n^(k-1))      (Eq. 19).
     Slices n < k are already exact after k iterations (the fine solution
     has propagated through them), so F is applied from slice k-1 on and
     U_k^k is F(U_(k-1)^(k-1)) itself.  The defect between consecutive

@@ -80,7 +80,7 @@ struct GridPlan {
   int Nx = 0, Nz = 0, Mx = 0, Px = 0, Pz = 0, n = 0;
   double Ra = 0, Pr = 0, Lx = 0, Lz = 0, dt = 0, nu = 0, kappa = 0, scale = 0;
   double T_bot = 1, T_top = 0;
-  bool flux = false;              // fixed-flux temperature walls (Eq. 5)
+  bool flux = false;              // fixed-flux temperature walls (Eq. 7)
   bool urgent = false;            // coarse grid: the serial sweep is the critical path
   bool one_xcd = false;           // see GridDev::one_xcd
   int scheme = 4;

@@ -1,4 +1,4 @@
-// Parareal (section 3.1, Eq. 13) around the batched fine propagator: the
+// Parareal (section 3.1, Eq. 19) around the batched fine propagator: the
 // serial coarse sweep, the sweep-then-batch iteration, and the pipelined
 // iteration, a host scheduler that overlaps the two propagators on two
 // streams.
@@ -82,8 +82,8 @@ rbc_status read_defect(rbc_handle h, int first, int last, double* defect, bool* 
 
 // Time averages over [nu_t_start, t_end] of the diagnostic samples of slices
 // [0, S) (slice(n) points at slice n's [ns][kDiag] records), the consistency
-// checks of section 2.2: out = (Nu_V, Nu_b, Nu_t, Nu_int (Eq. 11), KE, Re,
-// epsilon_U, P, |P - epsilon_U| / P (Eq. 12)); Re is the mean RMS velocity
+// checks of section 2.2: out = (Nu_V, Nu_b, Nu_t, Nu_int (Eq. 13), KE, Re,
+// epsilon_U, P, |P - epsilon_U| / P (Eq. 15)); Re is the mean RMS velocity
 // <u^2 + w^2>^(1/2) = (2 KE)^(1/2) over the viscosity.  Fixed summation
 // order.
 template <typename SliceFn>

@@ -7,7 +7,7 @@ at every slice boundary, so one run gives, for every iteration k,
   - the L2 error of U_k against the serial fine solution, at the final time
     and the maximum over slice boundaries,
   - the error of the time-averaged Nu_V against the serial fine run's, and
-    the internal checks Nu_int (Eq. 11) and |P - epsilon_U|/P (Eq. 12)
+    the internal checks Nu_int (Eq. 13) and |P - epsilon_U|/P (Eq. 15)
     (Figs. 7-9),
   - the kinetic energy at every slice boundary (Fig. 5),
   - the wall time at which iteration k was complete (pipelined schedule),

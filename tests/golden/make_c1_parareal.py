@@ -1,4 +1,4 @@
-"""Writes c1_parareal.json: the oracle's Parareal (section 3.1, Eq. 13) at the
+"""Writes c1_parareal.json: the oracle's Parareal (section 3.1, Eq. 19) at the
 64x32, 4-slice workload (Ra 1e4, Pr 1, 2x1 box, ARS(2,2,2), FP64, t in
 [0, 10], fine step 1e-3, coarse propagator on the same grid at step 1e-2),
 from the seeded initial state of section 2.1, run to finite termination

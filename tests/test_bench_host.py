@@ -38,10 +38,10 @@ def test_time_averages_follow_section_2_2():
     out = bench.diag_time_averages(rec, visc)
     nv, nb, nt = 3.0, 3.0, 3.0
     assert np.allclose(out[:3], [nv, nb, nt])
-    assert out[3] == 0.0                                   # Nu_int (Eq. 11)
+    assert out[3] == 0.0                                   # Nu_int (Eq. 13)
     assert np.isclose(out[4], 1.25)                        # KE
     assert np.isclose(out[5], (1.0 + 2.0) / 2 / visc)      # Re = <sqrt(2 KE)> / nu
-    assert np.isclose(out[8], abs(0.020 - 0.020) / 0.020)  # |P - eps_U| / P (Eq. 12)
+    assert np.isclose(out[8], abs(0.020 - 0.020) / 0.020)  # |P - eps_U| / P (Eq. 15)
 
 
 def test_traffic_summary_is_ignored_for_another_workload():

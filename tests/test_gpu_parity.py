@@ -494,7 +494,7 @@ def test_parareal_statistics_based_stop():
 
 
 
-# ---------------------------------------------- fixed-flux walls (Eq. 5) ---
+# ---------------------------------------------- fixed-flux walls (Eq. 7) ---
 
 def test_init_state_fixed_flux_matches_oracle():
     p = params(32, 16, Ra=1e5, dt=2e-3, bc_T=R().RBC_BC_FLUX)

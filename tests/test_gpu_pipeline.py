@@ -1,6 +1,6 @@
 """The pipelined Parareal iteration (coarse sweep overlapped with the fine
 runs on two streams, fine runs of different slices and iterations batched in
-one ring) against the sweep-then-batch order of the same library: Eq. 13
+one ring) against the sweep-then-batch order of the same library: Eq. 19
 fixes every iterate, so the two must agree bit for bit, in the states, the
 defects, the Nu histories, the stop iteration and the precision switch.
 The sweep-then-batch order itself is checked against the oracle in

@@ -556,7 +556,7 @@ def test_energy_budget_matches_time_derivative():
 
 
 def test_time_averages_of_the_consistency_checks():
-    """Eq. 11 and the balance of Eq. 12 on hand-made records; Re is the mean
+    """Eq. 13 and the balance of Eq. 15 on hand-made records; Re is the mean
     RMS velocity over the viscosity."""
     g = O.Grid(1e6, 1.0, 2.0, 1.0, 16, 8, 1.0)
     s = np.array([[8.0, 7.9, 8.2, 0.02, 0.0070, 0.0071],
@@ -570,7 +570,7 @@ def test_time_averages_of_the_consistency_checks():
 
 
 
-# ------------------------------------------------ fixed-flux walls (Eq. 5) ---
+# ------------------------------------------------ fixed-flux walls (Eq. 7) ---
 
 @pytest.mark.parametrize("m", [0, 1, 5])
 def test_tau_solve_recovers_manufactured_temperature_fixed_flux(m):
@@ -627,3 +627,153 @@ def test_fixed_flux_onset_tends_to_720():
           for kk in (0.04, 0.02)]
     assert abs(ra[1] - 720.0) < 0.05, ra
     assert ra[0] > ra[1] > 720.0 - 1e-6 and abs((ra[0] - 720) / (ra[1] - 720) - 4) < 0.1, ra
+
+
+# ------------------------------------ advective terms (section 2.1, Eqs. 3-5) ---
+#
+# A manufactured, band-limited flow is written as an exact trigonometric
+# polynomial in x times ordinary polynomials in z, with a mean shear u_bar(z)
+# and tilted rolls (so that <u w> and d u_bar/dz are both nonzero).  The
+# advection of momentum and heat is evaluated from the primitive variables
+# u, w, T with exact derivatives and exact products, and compared with the
+# oracle's pseudo-spectral explicit terms.  Low polynomial degrees keep every
+# product inside the retained spectrum, so the comparison is exact to
+# rounding.
+
+class _TrigPoly:
+    """f(x, z) = sum_m c_m(z) exp(i m k x), c_m numpy Polynomials in z, with
+    c_(-m) = conj(c_m) for a real field."""
+
+    def __init__(self, k, coeffs):
+        self.k = k
+        self.c = {m: p for m, p in coeffs.items()}
+
+    @staticmethod
+    def real_field(k, modes):
+        """modes: {m >= 0: complex Polynomial c_m}; adds the conjugate modes."""
+        c = {}
+        for m, p in modes.items():
+            c[m] = p
+            if m > 0:
+                c[-m] = np.polynomial.Polynomial(np.conj(p.coef))
+        return _TrigPoly(k, c)
+
+    def __add__(self, o):
+        c = dict(self.c)
+        for m, p in o.c.items():
+            c[m] = c[m] + p if m in c else p
+        return _TrigPoly(self.k, c)
+
+    def __sub__(self, o):
+        return self + o.scale(-1.0)
+
+    def scale(self, a):
+        return _TrigPoly(self.k, {m: p * a for m, p in self.c.items()})
+
+    def __mul__(self, o):
+        c = {}
+        for m1, p1 in self.c.items():
+            for m2, p2 in o.c.items():
+                m = m1 + m2
+                c[m] = c[m] + p1 * p2 if m in c else p1 * p2
+        return _TrigPoly(self.k, c)
+
+    def dx(self):
+        return _TrigPoly(self.k, {m: p * (1j * m * self.k) for m, p in self.c.items()})
+
+    def dz(self):
+        return _TrigPoly(self.k, {m: p.deriv() for m, p in self.c.items()})
+
+    def mode(self, m):
+        return self.c.get(m, np.polynomial.Polynomial([0.0]))
+
+
+def _cheb_of_complex(p, Lz, N):
+    return _cheb_of(lambda z: p(z).real, Lz, N) + 1j * _cheb_of(lambda z: p(z).imag, Lz, N)
+
+
+def _sheared_rolls(g, b=0.4, c=0.3, e=0.2):
+    """Streamfunction with tilted rolls in modes 1 and 2, a no-slip mean
+    shear u_bar and a perturbed temperature, as exact trigonometric
+    polynomials and as an oracle state."""
+    P = np.polynomial.Polynomial
+    k = g.k[1]
+    zz = P([0, 0, 1, -2, 1])                                  # z^2 (1-z)^2: psi = psi_z = 0 on the walls
+    psi = _TrigPoly.real_field(k, {1: zz * P([0.5 * b, -0.6j * b, 0.3j * b]),   # phase varies with z
+                                   2: zz * P([0.2 * b + 0.1j * b, 0.25 * b])})
+    ubar = P([0, 1, -1]) * P([c, -0.7 * c, 0.9 * c])           # u_bar(0) = u_bar(1) = 0, sheared
+    Tf = _TrigPoly.real_field(k, {0: P([1.0, -1.0]) + P([0, 1, -1]) * P([0.1]),
+                                  1: P([0, 1, -1]) * P([0.5 * e, 0.3j * e]),
+                                  2: P([0, 1, -1]) * P([0.1j * e, -0.2 * e])})
+    u = psi.dz() + _TrigPoly(k, {0: ubar})
+    w = psi.dx().scale(-1.0)
+    X = O.State(np.zeros((g.Mx, g.Nz), complex), np.zeros((g.Mx, g.Nz), complex))
+    for m in range(g.Mx):
+        X.T[m] = _cheb_of_complex(Tf.mode(m), g.Lz, g.Nz)
+        if m > 0:
+            X.P[m] = _cheb_of_complex(psi.mode(m), g.Lz, g.Nz)
+    X.P[0] = _cheb_of(ubar, g.Lz, g.Nz)
+    return u, w, Tf, X
+
+
+def test_advective_terms_equal_primitive_variable_advection():
+    """The explicit terms of the stepper against the advection written in
+    primitive variables: the curl of (u.grad)u (vorticity omega = u_z - w_x
+    of the streamfunction form), (u.grad)T, and for the mean flow the
+    horizontal mean of the x-component of (u.grad)u, each moved to the left
+    of the equation (hence the minus sign) and into the equation's basis.
+    A flipped sign of the vorticity advection or of the mean-flow forcing,
+    or a dropped term, fails here."""
+    g = O.Grid(1e5, 1.0, 2.0, 1.0, 16, 32, 1e-3)
+    u, w, Tf, X = _sheared_rolls(g)
+    ax = u * u.dx() + w * u.dz()                   # x-component of (u.grad)u
+    az = u * w.dx() + w * w.dz()                   # z-component
+    curl = ax.dz() - az.dx()                       # omega = u_z - w_x
+    adv_T = u * Tf.dx() + w * Tf.dz()
+    ops = O.Operators(g)
+    E = O.Stepper(g).explicit(X)
+    def close(got, want):
+        return np.abs(got - want).max() <= 1e-12 * max(np.abs(want).max(), 1e-3)
+
+    for m in range(1, g.Mx):
+        want = -(ops.S3210 @ _cheb_of_complex(curl.mode(m), g.Lz, g.Nz))
+        assert close(E.P[m], want), m
+    for m in range(g.Mx):
+        want = -(ops.S10 @ _cheb_of_complex(adv_T.mode(m), g.Lz, g.Nz))
+        assert close(E.T[m], want), m
+    want_u = -(ops.S10 @ _cheb_of_complex(ax.mode(0), g.Lz, g.Nz))
+    assert close(E.P[0], want_u)
+    # the manufactured flow does exercise every term: mean-flow forcing,
+    # vorticity advection in modes 1..4 (products of modes 1 and 2)
+    assert np.abs(want_u).max() > 1e-4
+    assert min(np.abs(E.P[m]).max() for m in (1, 2, 3, 4)) > 1e-4
+
+
+def test_mean_flow_forcing_is_minus_the_reynolds_stress_gradient():
+    """x-average of (u.grad)u = d<u w>/dz for the divergence-free flow, and
+    the oracle's mean-flow term is -S1 D1 of its dealiased <u w>."""
+    g = O.Grid(1e5, 1.0, 2.0, 1.0, 16, 32, 1e-3)
+    u, w, _, X = _sheared_rolls(g)
+    uw = (u * w).mode(0)
+    ax = (u * u.dx() + w * u.dz()).mode(0)
+    zs = np.linspace(0, 1, 11)
+    assert np.allclose(ax(zs), uw.deriv()(zs), atol=1e-13)
+    _, _, q_hat = O.nonlinear_terms(g, X)
+    assert np.allclose(q_hat, _cheb_of_complex(uw, g.Lz, g.Nz), atol=1e-13)
+
+
+def test_energy_budget_with_mean_shear_and_tilted_rolls():
+    """d(KE)/dt = P - epsilon_U along a time-stepped solution that starts
+    from strong mean shear and tilted rolls: the exchange between mean flow
+    and rolls (Reynolds stress times shear) enters the mean-flow and the
+    roll energy with opposite signs, so a sign error in either advective
+    term, or a dropped mean-flow forcing, breaks the budget."""
+    g = O.Grid(2e4, 1.0, 2.0, 1.0, 16, 24, 2e-3)
+    _, _, _, X = _sheared_rolls(g, b=2.0, c=1.5, e=0.5)
+    st = O.Stepper(g)
+    Xm = st.step(X)
+    X0 = st.step(Xm)
+    Xp = st.step(X0)
+    dke = (O.kinetic_energy(g, Xp) - O.kinetic_energy(g, Xm)) / (2 * g.dt)
+    budget = O.buoyancy_production(g, X0) - O.viscous_dissipation(g, X0)
+    assert abs(dke - budget) < 1e-4 * abs(budget), (dke, budget)
