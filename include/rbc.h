@@ -221,6 +221,29 @@ rbc_status parareal_iterate(rbc_handle h, double* U_dev, int32_t k_max, double t
                             int32_t* k_done_host, double* defect_hist_host,
                             double* nu_avg_hist_host);
 
+/* Checkpoint and resume of the Parareal iteration at an iteration boundary
+ * (section 3.1, Eq. 19).  Iteration k + 1 reads the iterate U^k, the coarse
+ * propagation G(U_n^k) of every slice, and the decisions and averages of
+ * iteration k; U^k is the caller's U_dev, the rest lives in the handle.
+ * rbc_get_state copies the rest, as left by the last parareal_iterate on
+ * h, into host memory buf of *bytes bytes (buf = NULL: *bytes gets the size
+ * needed, which depends only on the parameters): the iteration k reached,
+ * its defect and the previous one, the FP64-switch iterations, the time
+ * averages of iteration k, the coarse parts of G(U_n^k) and each slice's
+ * diagnostic samples from its latest fine run.  Synchronises.
+ * RBC_ERR_STATE if no parareal_iterate has run on h.
+ * rbc_set_state loads such a buffer into a handle created with the same
+ * slices, grids and sampling (RBC_ERR_ARG otherwise); the next
+ * parareal_iterate on h, called with U_dev = the saved U^k, then continues
+ * at iteration k + 1 instead of starting with the coarse prediction: its
+ * iterates, defects (defect_hist_host[j-1] for j > k) and averages
+ * (nu_avg_hist_host[j] for j >= k) are those of the uninterrupted run, bit
+ * for bit, in either schedule; k_max counts from iteration 0.  The buffer
+ * format is the library's own (native byte order), not a file format for
+ * other machines. */
+rbc_status rbc_get_state(rbc_handle h, void* buf, size_t* bytes);
+rbc_status rbc_set_state(rbc_handle h, const void* buf, size_t bytes);
+
 /* Iterate history for studies of the convergence (section 4): later
  * parareal_iterate calls copy U_dev ([n_slices+1][state]) after the coarse
  * prediction and after each iteration k <= k_cap into

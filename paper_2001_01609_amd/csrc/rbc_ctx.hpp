@@ -40,6 +40,19 @@ struct rbc_ctx {
   // built at the first pipelined iteration that needs them
   hipGraphExec_t cgraph = nullptr, cgraph64 = nullptr;
   rbc_pipeline_stats pstats{};  // statistics of the last pipelined iteration
+  // Where the last parareal_iterate ended (rbc_get_state): iterations done,
+  // the last two defects, the precision-switch iterations as they stood
+  // before the switch test of that last iteration, and its time averages.
+  // `resume` (rbc_set_state) is the same record, consumed by the next
+  // parareal_iterate, which then continues at iteration k + 1.
+  struct IterState {
+    int k = -1;
+    int kG64 = 0, kF64 = 0;     // INT_MAX: not switched
+    double defect = 0, prev = 0;
+    int has_avg = 0;
+    double avg[rbc::kDiagAvg] = {};
+  };
+  IterState last, resume;
   rbc::KernelTiming timing;    // fine-grid kernel timing (rbc_kernel_timing_*)
   std::string err;
 };

@@ -38,6 +38,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstring>
 #include <climits>
 #include <cmath>
 #include <mutex>
@@ -153,28 +154,67 @@ bool promote_now(rbc_handle h, int k, double d, double prev, double tol) {
   return h->has64 && k >= 2 && ((tol < 1e-6 && d <= 1e-3) || (d <= 1e-4 && d > 0.5 * prev));
 }
 
+// Records where an iteration ended (rbc_get_state): before the precision
+// switch test of iteration k, which a resumed run makes first.
+void record_iteration(rbc_handle h, int k, int kG64, int kF64, double defect, double prev, const double* avg) {
+  rbc_ctx::IterState& r = h->last;
+  r.k = k;
+  r.kG64 = kG64;
+  r.kF64 = kF64;
+  r.defect = defect;
+  r.prev = prev;
+  r.has_avg = avg ? 1 : 0;
+  for (int c = 0; c < rbc::kDiagAvg; ++c) r.avg[c] = avg ? avg[c] : 0.0;
+}
+
+// Start of a resumed iteration: the record's switch test of iteration k (as
+// the uninterrupted run makes it after reading k's defect), its averages in
+// nu_hist[k].
+void resume_start(rbc_handle h, const rbc_ctx::IterState& r, double tol, bool want_nu, double* nu_hist, int* kG64,
+                  int* kF64, double* defect, double* prev) {
+  *kG64 = r.kG64;
+  *kF64 = r.kF64;
+  *defect = r.defect;
+  *prev = r.prev;
+  if (*kG64 == INT_MAX && r.k >= 1 && promote_now(h, r.k, r.defect, r.prev, tol)) {
+    *kG64 = r.k + 1;
+    *kF64 = r.k + 2;
+  }
+  *prev = r.defect;
+  if (want_nu)
+    for (int c = 0; c < rbc::kDiagAvg; ++c) nu_hist[size_t(rbc::kDiagAvg) * r.k + c] = r.has_avg ? r.avg[c] : NAN;
+}
+
 // ---------------------------------------------------------------- sweep-then-batch ---
 
 rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, int* k_done, double* defect_hist,
-                               double* nu_hist) {
+                               double* nu_hist, const rbc_ctx::IterState* from) {
   const int S = h->p.n_slices;
   const size_t fs = h->fine.dev.state;
   const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
   rbc_status s;
   *k_done = 0;
-  if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
-  if ((s = save_iterate(h, U, 0, h->stream)) != RBC_OK) return s;
-  if (want_nu) {
-    if (h->nsc > 0) {
-      if ((s = diag_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, h->coarse.dev.nu, nu_hist)) != RBC_OK)
-        return s;
-    } else {
-      for (int c = 0; c < rbc::kDiagAvg; ++c) nu_hist[c] = NAN;
-    }
-  }
-  h->stop_reason = RBC_STOP_KMAX;
   double defect = INFINITY, prev = INFINITY;
   int k = 0, kG64 = INT_MAX, kF64 = INT_MAX;
+  if (from) {
+    k = from->k;
+    *k_done = k;
+    resume_start(h, *from, tol, want_nu, nu_hist, &kG64, &kF64, &defect, &prev);
+  } else {
+    if ((s = sweep(h, 0, 0, U, nullptr, h->Gbuf, want_nu && h->nsc > 0)) != RBC_OK) return s;
+    if ((s = save_iterate(h, U, 0, h->stream)) != RBC_OK) return s;
+    if (want_nu) {
+      if (h->nsc > 0) {
+        if ((s = diag_average(h, h->nu_c, h->nsc, h->stride_c, h->coarse.dt, h->coarse.dev.nu, nu_hist)) != RBC_OK)
+          return s;
+      } else {
+        for (int c = 0; c < rbc::kDiagAvg; ++c) nu_hist[c] = NAN;
+      }
+    }
+    RBC_HIPCHK(h, hipStreamSynchronize(h->stream));
+    record_iteration(h, 0, kG64, kF64, defect, prev, want_nu ? nu_hist : nullptr);
+  }
+  h->stop_reason = RBC_STOP_KMAX;
   while (k < k_max && k < S) {
     ++k;
     // F on slices k-1..S-1 from U^(k-1)
@@ -199,6 +239,7 @@ rbc_status parareal_sequential(rbc_handle h, double* U, int k_max, double tol, i
     if (want_nu && (s = diag_average(h, h->nu_f, h->nsf, h->p.nu_stride, h->fine.dt, h->fine.dev.nu,
                                      nu_hist + rbc::kDiagAvg * k)) != RBC_OK)
       return s;
+    record_iteration(h, k, kG64, kF64, defect, prev, want_nu ? nu_hist + rbc::kDiagAvg * k : nullptr);
     if (bad) return fail(h, RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
     if (defect <= tol) {
       h->stop_reason = RBC_STOP_DEFECT;
@@ -237,19 +278,33 @@ struct Job {
 
 class Pipeline {
  public:
+  // from: a checkpoint (rbc_set_state) to continue at iteration from->k + 1,
+  // or null to start with the coarse prediction.
   Pipeline(rbc_handle h, double* U, int K, double tol, bool want_nu, int* k_done, double* defect_hist,
-           double* nu_hist)
-      : h_(h), U_(U), S_(h->p.n_slices), K_(K), nf_(h->nf), nc_(h->nc), cap_(h->ring_cap),
+           double* nu_hist, const rbc_ctx::IterState* from)
+      : h_(h), U_(U), S_(h->p.n_slices), K_(K), k0_(from ? from->k : 0), resumed_(from != nullptr),
+        nf_(h->nf), nc_(h->nc), cap_(h->ring_cap),
         stride_(h->p.nu_stride), tol_(tol), want_nu_(want_nu), k_done_(k_done), defect_hist_(defect_hist),
         nu_hist_(nu_hist), fs_(h->fine.dev.state), cs_(h->coarse.dev.state), F_(h->fstream), G_(h->gstream),
-        F64_(h->f64stream ? h->f64stream : h->fstream) {}
+        F64_(h->f64stream ? h->f64stream : h->fstream) {
+    if (from) {
+      int g64 = INT_MAX, f64 = INT_MAX;
+      resume_start(h, *from, tol, want_nu, nu_hist, &g64, &f64, &defect_, &prev_);
+      kG64_ = g64;
+      kF64_ = f64;
+      processed_ = k0_;
+      *k_done = k0_;
+    }
+  }
 
   rbc_status run();
 
  private:
   rbc_handle h_;
   double* U_;
-  const int S_, K_, nf_, nc_, cap_, stride_;
+  const int S_, K_, k0_;      // k0_: iterations done before this call (resumed) or 0
+  const bool resumed_;
+  const int nf_, nc_, cap_, stride_;
   const double tol_;
   const bool want_nu_;
   int* k_done_;
@@ -290,6 +345,7 @@ class Pipeline {
   int job_index(int k, int n) const { return job_base_[k] + (n - (k - 1)); }
   int producer(const Job& J) const {
     if (J.n == 0) return -1;                                          // U_0
+    if (J.k == k0_ + 1 && resumed_) return -1;                        // U^(k0) of the checkpoint
     if (J.k == 1) return J.n - 1;                                     // Predict(0, n-1)
     if (J.n == J.k - 1) return task_base_[J.k - 1];                   // Copy(k-1)
     return task_base_[J.k - 1] + 1 + (J.n - 1 - (J.k - 1));           // Correct(k-1, n-1)
@@ -367,14 +423,16 @@ rbc_status Pipeline::build_graph(rbc::GridPlan& cp, rbc::Work& cw, hipGraphExec_
 rbc_status Pipeline::setup() {
   rbc_status s_;
   for (int k = 0; k <= K_; ++k) job_base_.push_back(0);
-  for (int k = 1; k <= K_; ++k) {
+  for (int k = k0_ + 1; k <= K_; ++k) {
     job_base_[k] = int(jobs_.size());
     for (int n = k - 1; n < S_; ++n) jobs_.push_back({k, n, int(jobs_.size() % cap_), -1, false});
   }
   task_base_.assign(K_ + 1, 0);
-  for (int n = 0; n < S_; ++n) tasks_.push_back({kPredict, 0, n});
-  tasks_.push_back({kReport, 0, -1});
-  for (int k = 1; k <= K_; ++k) {
+  if (!resumed_) {
+    for (int n = 0; n < S_; ++n) tasks_.push_back({kPredict, 0, n});
+    tasks_.push_back({kReport, 0, -1});
+  }
+  for (int k = k0_ + 1; k <= K_; ++k) {
     task_base_[k] = int(tasks_.size());
     tasks_.push_back({kCopy, k, k - 1});
     for (int n = k; n < S_; ++n) tasks_.push_back({kCorrect, k, n});
@@ -629,6 +687,7 @@ int Pipeline::poll_report() {
       else
         for (int c = 0; c < rbc::kDiagAvg; ++c) nu_hist_[c] = NAN;
     }
+    record_iteration(h_, 0, kG64_, kF64_, defect_, prev_, want_nu_ ? nu_hist_ : nullptr);
     if (K_ == 0) stop_ = true;
     return 1;
   }
@@ -646,6 +705,7 @@ int Pipeline::poll_report() {
                       },
                       nu_hist_ + rbc::kDiagAvg * k);
   }
+  record_iteration(h_, k, kG64_, kF64_.load(), defect_, prev_, want_nu_ ? nu_hist_ + rbc::kDiagAvg * k : nullptr);
   if (bad) {
     seterr(RBC_ERR_NONFINITE, "non-finite value in Parareal iteration " + std::to_string(k));
     return 1;
@@ -706,7 +766,7 @@ void Pipeline::fine_loop() {
 
 rbc_status Pipeline::run() {
   using clk = std::chrono::steady_clock;
-  *k_done_ = 0;
+  *k_done_ = k0_;
   h_->stop_reason = RBC_STOP_KMAX;
   rbc_status s = setup();
   if (s != RBC_OK) return s;
@@ -808,10 +868,130 @@ rbc_status parareal_iterate(rbc_handle h, double* U, int32_t k_max, double tol, 
   if (k_max < 0) return fail(h, RBC_ERR_ARG, "k_max < 0");
   h->k_fp64 = 0;
   h->stop_reason = -1;
-  if (!h->p.pipelined) return parareal_sequential(h, U, k_max, tol, k_done, defect_hist, nu_hist);
+  // a checkpoint set by rbc_set_state is consumed by this call
+  const rbc_ctx::IterState from = h->resume;
+  h->resume = rbc_ctx::IterState{};
+  const rbc_ctx::IterState* fp = from.k >= 0 ? &from : nullptr;
+  const int K = std::min<int>(k_max, h->p.n_slices);
+  if (fp && fp->k >= K) {
+    // nothing left to do: the checkpoint already holds iteration K
+    *k_done = fp->k;
+    h->last = from;
+    h->stop_reason = (fp->k == h->p.n_slices) ? RBC_STOP_EXACT : RBC_STOP_KMAX;
+    return RBC_OK;
+  }
+  if (!h->p.pipelined) return parareal_sequential(h, U, k_max, tol, k_done, defect_hist, nu_hist, fp);
   const bool want_nu = nu_hist && h->p.nu_stride > 0 && h->nsf > 0;
-  Pipeline pl(h, U, std::min<int>(k_max, h->p.n_slices), tol, want_nu, k_done, defect_hist, nu_hist);
+  Pipeline pl(h, U, K, tol, want_nu, k_done, defect_hist, nu_hist, fp);
   return pl.run();
+}
+
+// ------------------------------------------------------------ checkpoints ---
+//
+// Layout of a checkpoint (host memory, native byte order):
+//   char[8] "RBCCKPT1";
+//   int64 n_slices, fine state doubles, coarse state doubles, samples per
+//         slice (nsf), k, kG64, kF64, has_avg;
+//   double defect, prev, avg[RBC_DIAG_AVG];
+//   double G[n_slices][coarse state]        the coarse part of G(U_n^k);
+//   double samples[n_slices][nsf][RBC_DIAG]  slice n's diagnostic samples
+//         from its latest fine run (read by the time averages of later
+//         iterations for the slices that no longer run).
+namespace {
+constexpr char kCkptMagic[8] = {'R', 'B', 'C', 'C', 'K', 'P', 'T', '1'};
+constexpr size_t kCkptHead = 8 + 8 * 8 + (2 + rbc::kDiagAvg) * 8;
+
+size_t ckpt_bytes(rbc_handle h) {
+  const size_t S = h->p.n_slices;
+  return kCkptHead + S * h->coarse.dev.state * 8 + S * size_t(h->nsf) * rbc::kDiag * 8;
+}
+
+// Slot of slice n's latest samples in the handle's sample buffer after
+// iteration k (the pipelined schedule alternates two buffers by iteration
+// parity; the sweep-then-batch schedule keeps one).
+size_t sample_block(rbc_handle h, int k, int n) {
+  const size_t blk = size_t(h->nsf) * rbc::kDiag;
+  if (!h->p.pipelined) return size_t(n) * blk;
+  const int par = (n >= k - 1) ? (k & 1) : ((n + 1) & 1);
+  return (size_t(par) * h->p.n_slices + n) * blk;
+}
+}  // namespace
+
+extern "C" rbc_status rbc_get_state(rbc_handle h, void* buf, size_t* bytes) {
+  if (!h || !bytes) return fail(h, RBC_ERR_ARG, "null argument");
+  const size_t need = ckpt_bytes(h);
+  if (!buf) {
+    *bytes = need;
+    return RBC_OK;
+  }
+  if (*bytes < need) return fail(h, RBC_ERR_ARG, "checkpoint buffer too small: " + std::to_string(need) + " bytes");
+  if (h->last.k < 0) return fail(h, RBC_ERR_STATE, "no Parareal iteration to checkpoint");
+  const rbc_ctx::IterState& r = h->last;
+  const int S = h->p.n_slices;
+  unsigned char* o = static_cast<unsigned char*>(buf);
+  std::memcpy(o, kCkptMagic, 8);
+  const int64_t hi[8] = {S, int64_t(h->fine.dev.state), int64_t(h->coarse.dev.state), h->nsf,
+                         r.k, r.kG64, r.kF64, r.has_avg};
+  std::memcpy(o + 8, hi, sizeof(hi));
+  double hd[2 + rbc::kDiagAvg];
+  hd[0] = r.defect;
+  hd[1] = r.prev;
+  for (int c = 0; c < rbc::kDiagAvg; ++c) hd[2 + c] = r.avg[c];
+  std::memcpy(o + 8 + sizeof(hi), hd, sizeof(hd));
+  double* G = reinterpret_cast<double*>(o + kCkptHead);
+  const size_t cs = h->coarse.dev.state;
+  RBC_HIPCHK(h, hipMemcpyAsync(G, h->Gbuf, size_t(S) * cs * 8, hipMemcpyDeviceToHost, h->stream));
+  const size_t blk = size_t(h->nsf) * rbc::kDiag;
+  double* smp = G + size_t(S) * cs;
+  if (blk > 0 && h->nu_f)
+    for (int n = 0; n < S; ++n)
+      RBC_HIPCHK(h, hipMemcpyAsync(smp + n * blk, h->nu_f + sample_block(h, r.k, n), blk * 8, hipMemcpyDeviceToHost,
+                                   h->stream));
+  RBC_HIPCHK(h, hipStreamSynchronize(h->stream));
+  *bytes = need;
+  return RBC_OK;
+}
+
+extern "C" rbc_status rbc_set_state(rbc_handle h, const void* buf, size_t bytes) {
+  if (!h || !buf) return fail(h, RBC_ERR_ARG, "null argument");
+  if (bytes < kCkptHead) return fail(h, RBC_ERR_ARG, "checkpoint too short");
+  const unsigned char* in = static_cast<const unsigned char*>(buf);
+  if (std::memcmp(in, kCkptMagic, 8) != 0) return fail(h, RBC_ERR_ARG, "not a checkpoint (bad magic)");
+  int64_t hi[8];
+  std::memcpy(hi, in + 8, sizeof(hi));
+  const int S = h->p.n_slices;
+  if (hi[0] != S || hi[1] != int64_t(h->fine.dev.state) || hi[2] != int64_t(h->coarse.dev.state) ||
+      hi[3] != h->nsf)
+    return fail(h, RBC_ERR_ARG, "checkpoint of another configuration (slices, grids or sampling differ)");
+  if (bytes < ckpt_bytes(h)) return fail(h, RBC_ERR_ARG, "checkpoint too short");
+  if (hi[4] < 0 || hi[4] > S) return fail(h, RBC_ERR_ARG, "checkpoint iteration out of range");
+  double hd[2 + rbc::kDiagAvg];
+  std::memcpy(hd, in + 8 + sizeof(hi), sizeof(hd));
+  rbc_ctx::IterState r;
+  r.k = int(hi[4]);
+  r.kG64 = hi[5] >= INT_MAX ? INT_MAX : int(hi[5]);
+  r.kF64 = hi[6] >= INT_MAX ? INT_MAX : int(hi[6]);
+  r.has_avg = int(hi[7]);
+  r.defect = hd[0];
+  r.prev = hd[1];
+  for (int c = 0; c < rbc::kDiagAvg; ++c) r.avg[c] = hd[2 + c];
+  if (!h->has64) r.kG64 = r.kF64 = INT_MAX;   // this handle has no FP64 propagators
+  const double* G = reinterpret_cast<const double*>(in + kCkptHead);
+  const size_t cs = h->coarse.dev.state;
+  RBC_HIPCHK(h, hipMemcpyAsync(h->Gbuf, G, size_t(S) * cs * 8, hipMemcpyHostToDevice, h->stream));
+  const size_t blk = size_t(h->nsf) * rbc::kDiag;
+  const double* smp = G + size_t(S) * cs;
+  // each slice's samples where the next iteration reads those of slices that
+  // no longer run: the one buffer, or the parity buffer of iteration n + 1
+  if (blk > 0 && h->nu_f)
+    for (int n = 0; n < S; ++n) {
+      const size_t at = h->p.pipelined ? (size_t((n + 1) & 1) * S + n) * blk : size_t(n) * blk;
+      RBC_HIPCHK(h, hipMemcpyAsync(h->nu_f + at, smp + n * blk, blk * 8, hipMemcpyHostToDevice, h->stream));
+    }
+  RBC_HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->resume = r;
+  h->last = r;
+  return RBC_OK;
 }
 
 rbc_status rbc_get_pipeline_stats(rbc_handle h, rbc_pipeline_stats* out) {

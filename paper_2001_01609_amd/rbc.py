@@ -102,6 +102,8 @@ def _load():
         "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64), P(dbl)]),
         "rbc_synchronize": (st, [vp]),
         "rbc_get_pipeline_stats": (st, [vp, P(rbc_pipeline_stats)]),
+        "rbc_get_state": (st, [vp, vp, P(ctypes.c_size_t)]),
+        "rbc_set_state": (st, [vp, vp, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -195,6 +197,20 @@ def parareal_iterate(h, U, k_max: int, tol: float, want_nu: bool = False):
         nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_nu else None), h)
     kd = k.value
     return st, kd, defects[:kd].copy(), (nu[: kd + 1].copy() if want_nu else None)
+
+
+def rbc_get_state(h) -> bytes:
+    """The handle's Parareal checkpoint after the last parareal_iterate."""
+    n = ctypes.c_size_t()
+    _check(_lib.rbc_get_state(h, None, ctypes.byref(n)), h)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(_lib.rbc_get_state(h, buf, ctypes.byref(n)), h)
+    return buf.raw[: n.value]
+
+
+def rbc_set_state(h, ckpt: bytes) -> None:
+    buf = ctypes.create_string_buffer(bytes(ckpt), len(ckpt))
+    _check(_lib.rbc_set_state(h, buf, len(ckpt)), h)
 
 
 def rbc_set_iterate_history(h, U_hist, k_cap: int) -> None:

@@ -15,6 +15,8 @@ import pytest
 
 import rbc_inputs as I
 from oracle import rbc_oracle as O
+from parity_util import (NoAdvectionStepper, assert_blocks, assert_sensitive, block_errors,
+                         developed_state)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -75,10 +77,6 @@ def to_dev(v):
     return torch.tensor(np.asarray(v), dtype=torch.float64, device=dev())
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
-
-
 def band_mask(g):
     """True on the equation rows (the wall-condition rows are zero on the GPU)."""
     m = np.zeros((2, g.Mx, 2, g.Nz), dtype=bool)
@@ -124,9 +122,9 @@ def test_explicit_terms_match_oracle(Nx, Nz, mixed):
         R().rbc_destroy(h)
     ref = O.Stepper(g).explicit(X).pack()
     m = band_mask(g)
-    err = np.linalg.norm(got[m] - ref[m]) / np.linalg.norm(ref[m])
-    assert err < (1e-5 if mixed else 1e-12), err
     assert not got[~m].any()
+    ref[~m] = 0.0
+    assert_blocks(got, ref, g, 1e-5 if mixed else 1e-12, "explicit terms")
 
 
 @pytest.mark.parametrize("scheme", [2, 4])
@@ -145,7 +143,7 @@ def test_one_fine_step_fp64(Nx, Nz, scheme):
     finally:
         R().rbc_destroy(h)
     ref = O.Stepper(g).step(X).pack()
-    assert rel(got, ref) < 1e-13
+    assert_blocks(got, ref, g, 1e-13, "one step")
 
 
 @pytest.mark.parametrize("tile", [None, "6"])
@@ -169,7 +167,7 @@ def test_batch_of_slices_many_steps_fp64(tile, monkeypatch):
         R().rbc_destroy(h)
     st = O.Stepper(g)
     for i, X in enumerate(Xs):
-        assert rel(got[i], st.run(X, 25).pack()) < FP64_TOL, i
+        assert_blocks(got[i], st.run(X, 25).pack(), g, FP64_TOL, f"slice {i}")
 
 
 @pytest.mark.parametrize("scheme", [2, 4])
@@ -191,7 +189,7 @@ def test_mixed_precision_steps_within_bar(scheme):
     st = O.Stepper(g)
     for i, X in enumerate(Xs):
         Y = st.run(X, 50)
-        assert rel(got[i], Y.pack()) < MIXED_TOL
+        assert_blocks(got[i], Y.pack(), g, MIXED_TOL, f"slice {i}")
         nref = np.array(O.nusselt(g, Y))
         assert np.all(np.abs(nu[i] - nref) / np.abs(nref) < 1e-4)
 
@@ -276,7 +274,7 @@ def test_parareal_matches_oracle_iterates():
             R().rbc_destroy(h)
         assert kd == k_max
         for nn in range(p.n_slices + 1):
-            assert rel(got[nn], ref.U[nn]) < FP64_TOL, (k_max, nn)
+            assert_blocks(got[nn], ref.U[nn], fine, FP64_TOL, f"k_max {k_max} slice {nn}")
         assert np.allclose(defects, ref.defects, rtol=1e-8, atol=1e-14)
 
 
@@ -350,32 +348,68 @@ def test_parareal_stops_at_tolerance_and_tracks_nu():
     assert np.all(nu[1:, :3] > 0.99)
 
 
-@pytest.mark.parametrize("w", [I.C2, I.C2_FP64, I.C3])
-def test_fullsize_batch_sampled_slices(w):
-    """Full workload shapes (32 slices of 256x64, the benchmark's; 64 slices
-    of 1024x256): two batched steps, the first and last slices checked
-    against the oracle."""
-    p = R().params_from_workload(w)
-    case(f"full size {w.name}: {p.n_slices} slices, 2 steps")
-    g = grid(p)
+# Full workload shapes on developed flow.  Each case runs the kernel
+# instantiations of that workload's launches (32 slices of 256x64 at full
+# batch: the four-mode per-mode kernel and the four-row x-pass; 64 slices of
+# 1024x256; single-slice FP64 runs, the serial FP64 reference stepper) from
+# states with O(0.3) rolls, mean shear and mean-temperature bumps, and checks
+# the first and last slice block by block.  The oracle with advection
+# switched off must differ from the oracle by at least 100x the tolerance in
+# every block, so that the comparison can see the nonlinear terms.
+FULLSIZE = {
+    "ra1e6_256x64_s32_mixed": (I.C2, {}, 4),
+    "ra1e6_256x64_s32_fp64": (I.C2_FP64, {}, 4),
+    "ra1e6_256x64_serial_fp64": (I.C2_FP64, {"n_slices": 1}, 4),
+    "ra1e8_1024x256_s64_mixed": (I.C3, {}, 6),
+    "ra1e8_1024x256_serial_fp64": (I.C3, {"n_slices": 1, "precision": 0}, 6),
+}
+_ORACLE_CACHE = {}
+
+
+def _oracle_run(g, seed, steps, advect=True):
+    """Oracle result of `steps` steps from developed_state(g, seed), cached
+    per grid (the 1024x256 stepper is slow to build); BLAS limited to four
+    threads (small dense solves run slower on more)."""
+    from threadpoolctl import threadpool_limits
+    key = (g.Nx, g.Nz, g.dt, g.Ra, seed, steps, advect)
+    if key not in _ORACLE_CACHE:
+        with threadpool_limits(limits=4):
+            skey = (g.Nx, g.Nz, g.dt, g.Ra, advect)
+            if skey not in _ORACLE_CACHE:
+                _ORACLE_CACHE[skey] = (O.Stepper if advect else NoAdvectionStepper)(g)
+            _ORACLE_CACHE[key] = _ORACLE_CACHE[skey].run(developed_state(g, seed), steps).pack()
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("name", sorted(FULLSIZE))
+def test_fullsize_developed_flow_first_and_last_slice(name):
+    w, over, steps = FULLSIZE[name]
+    p = R().params_from_workload(w, **over)
+    mixed = p.precision == R().RBC_MIXED
+    S = p.n_slices
+    case(f"full size {name}: {S} slices of {p.Nx}x{p.Nz}, {steps} steps, developed flow")
     h = create(p)
     try:
         nf, dt = R().rbc_steps_per_slice(h, 0)
         g = grid(p, dt)
         n = R().rbc_state_size(h)
-        X0 = oracle_state(g, 0, 1e-3)
-        X1 = oracle_state(g, 31, 1e-1)
-        host = np.stack([X0.pack() if s % 2 == 0 else X1.pack() for s in range(p.n_slices)])
+        seeds = [100 + s for s in range(S)]
+        host = np.stack([developed_state(g, sd).pack() for sd in seeds])
         U = to_dev(host.reshape(-1))
-        R().rbc_fine_step_batch(h, U, U, p.n_slices, 2)
-        got = U.cpu().numpy().reshape(p.n_slices, n)
+        del host
+        R().rbc_fine_step_batch(h, U, U, S, steps)
+        got = U.view(S, n)[[0, S - 1]].cpu().numpy()
+        del U
     finally:
         R().rbc_destroy(h)
-    st = O.Stepper(g)
-    tol = MIXED_TOL if w.mixed else FP64_TOL
-    last = p.n_slices - 1   # odd: the second initial state
-    assert rel(got[0], st.run(X0, 2).pack()) < tol
-    assert rel(got[last], st.run(X1, 2).pack()) < tol
+    tol = MIXED_TOL if mixed else FP64_TOL
+    for i, sd in ((0, seeds[0]), (1, seeds[-1])):
+        ref = _oracle_run(g, sd, steps)
+        e = assert_blocks(got[i], ref, g, tol, f"{name} slice {'first' if i == 0 else 'last'}", dev_T0=True)
+        print(f"[case] {name} seed {sd}: per-block errors {e}", flush=True)
+    sens = assert_sensitive(_oracle_run(g, seeds[0], steps), _oracle_run(g, seeds[0], steps, advect=False), g, tol,
+                            name)
+    print(f"[case] {name}: advection-off differences {sens}", flush=True)
 
 
 def test_parareal_promotes_stalled_mixed_fine_sweeps_to_fp64():
@@ -411,7 +445,11 @@ def test_parareal_promotes_stalled_mixed_fine_sweeps_to_fp64():
         ref = V.cpu().numpy()
     finally:
         R().rbc_destroy(h)
-    assert rel(got, ref) < 1e-8
+    # the stop test bounds the change of the whole state vector (1e-10 of a
+    # norm the mean temperature dominates); the streamfunction and the
+    # temperature rolls are about a hundredth of that norm, so per block the
+    # bar is 1e-7 (without the switch the mixed floor leaves them near 1e-5)
+    assert_blocks(got, ref, g, 1e-7, "promoted Parareal vs serial FP64")
 
 
 # ------------------------------------------- consistency checks (section 2.2) ---
@@ -528,7 +566,7 @@ def test_steps_fixed_flux_match_oracle(Nx, Nz, mixed):
     finally:
         R().rbc_destroy(h)
     Y = O.Stepper(g).run(X, 5)
-    assert rel(got, Y.pack()) < (1e-6 if mixed else 1e-12)
+    assert_blocks(got, Y.pack(), g, 1e-6 if mixed else 1e-12, "fixed flux")
     ref = O.diagnostics(g, Y)
     tol = (1e-5 if mixed else 1e-11) * np.maximum(np.abs(ref), [1, 1, 1, 0, 0, 0]) + 1e-16
     assert np.all(np.abs(d - ref) <= tol), (d, ref)
@@ -574,7 +612,7 @@ def test_parareal_fixed_flux_matches_oracle_iterates():
     finally:
         R().rbc_destroy(h)
     for nn in range(p.n_slices + 1):
-        assert rel(got[nn], ref.U[nn]) < FP64_TOL, nn
+        assert_blocks(got[nn], ref.U[nn], fine, FP64_TOL, f"slice {nn}")
     assert np.allclose(defects, ref.defects, rtol=1e-8, atol=1e-14)
 
 
