@@ -286,6 +286,20 @@ rbc_status rbc_nusselt(rbc_handle h, const double* U_dev, int32_t n_states, doub
  * fine states into out_host[n_states][RBC_DIAG].  Synchronises. */
 rbc_status rbc_diagnostics(rbc_handle h, const double* U_dev, int32_t n_states, double* out_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * records of rbc_diagnostics written to caller-owned device memory
+ * out_dev[n_states][RBC_DIAG], enqueued on the handle's stream without
+ * waiting, and allocating nothing.  The partial sums go to a device scratch
+ * array of the library (1 MiB per GPU, held until the process ends), so
+ * n_states is limited to 1 MiB / (32 bytes x ceil(Nx/2 / max(1, 512/Nz)))
+ * states (64 at 1024 x 256, 2048 at 256 x 64); more gives RBC_ERR_ARG.
+ * Every call on a GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (other streams, other threads, other handles) race, so serialise
+ * them.  The scratch needs no clearing (every partial is written before it
+ * is read). */
+rbc_status rbc_diagnostics_noalloc(rbc_handle h, const double* U_dev, int32_t n_states, double* out_dev);
+
 /* Diagnostic: the explicit (advective) terms of one fine state in the
  * equations' bases: E_dev gets a state-shaped array whose field 0 holds
  * -S3S2S1S0 N_omega (m >= 1) and -S1 D1 <u w> (m = 0), field 1 holds

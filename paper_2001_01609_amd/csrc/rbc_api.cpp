@@ -247,6 +247,9 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
     return fail(nullptr, st, m);
   };
   if (he != hipSuccess) return bail(RBC_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  // the allocation-free entry points' scratch on this device (once per device)
+  if ((he = rbc::scratch_init(h->device)) != hipSuccess)
+    return bail(RBC_ERR_HIP, std::string("device scratch address: ") + hipGetErrorString(he));
   if ((he = rbc::upload_plan(h->fine)) != hipSuccess || (he = rbc::upload_plan(h->coarse)) != hipSuccess ||
       (h->has64 && ((he = rbc::upload_plan(h->fine64)) != hipSuccess ||
                     (he = rbc::upload_plan(h->coarse64)) != hipSuccess)))
@@ -415,6 +418,21 @@ rbc_status rbc_diagnostics(rbc_handle h, const double* U, int32_t n, double* out
   if (!h || !U || !out_host || n < 0) return fail(h, RBC_ERR_ARG, "bad argument");
   if (n == 0) return RBC_OK;
   return diag_states(h, U, n, out_host, "rbc_diagnostics");
+}
+
+rbc_status rbc_diagnostics_noalloc(rbc_handle h, const double* U, int32_t n, double* out_dev) {
+  if (!h || !U || !out_dev || n < 0) return fail(h, RBC_ERR_ARG, "bad argument");
+  if (n == 0) return RBC_OK;
+  const size_t per = rbc::diag_partials_per_state(h->fine.dev);
+  const size_t cap = rbc::kScratchBytes / sizeof(double) / per;
+  if (size_t(n) > cap)
+    return fail(h, RBC_ERR_ARG, "rbc_diagnostics_noalloc: " + std::to_string(n) + " states exceed the maximum of " +
+                                    std::to_string(cap) + " for this grid (" + std::to_string(rbc::kScratchBytes) +
+                                    " bytes of device scratch)");
+  double* part = rbc::scratch_ptr(h->device);
+  if (!part) return fail(h, RBC_ERR_STATE, "rbc_diagnostics_noalloc: device scratch not set up");
+  HIPCHK(h, rbc::launch_diag_into(h->fine, part, U, 0, n, n, out_dev, rbc::kDiag, nullptr, 0, 1, 0, 0, h->stream));
+  return RBC_OK;
 }
 
 rbc_status rbc_explicit_terms(rbc_handle h, const double* U, double* E) {

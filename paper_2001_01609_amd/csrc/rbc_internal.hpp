@@ -165,6 +165,18 @@ hipError_t launch_set_meta(SlotMeta* meta, int slot, SlotMeta v, hipStream_t st)
 // multiple q+1 of `stride` own steps writes out[((par S + n) nsf + q) kDiag].
 hipError_t launch_diag(const GridPlan& g, Work& w, const double* X, int slot0, int count, int cap, double* out,
                        int ld, const SlotMeta* meta, int t, int stride, int nsf, int S, hipStream_t st);
+// The same with the partial sums in `part` (diag_partials_per_state doubles
+// per state, count states) instead of the work buffers.
+hipError_t launch_diag_into(const GridPlan& g, double* part, const double* X, int slot0, int count, int cap,
+                            double* out, int ld, const SlotMeta* meta, int t, int stride, int nsf, int S,
+                            hipStream_t st);
+size_t diag_partials_per_state(const GridDev& d);
+// Device scratch of the allocation-free entry points (kScratchBytes per GPU,
+// a static device array): scratch_init takes its address on `device` (which
+// must be current) once; scratch_ptr returns it, or null before that.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+hipError_t scratch_init(int device);
+double* scratch_ptr(int device);
 // Explicit terms of one state (diagnostic): E = state-shaped FP64 array.
 hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* E, hipStream_t st);
 // Fine -> coarse restriction (truncation).

@@ -23,6 +23,8 @@
 // mixed-space arrays [slice][quantity][j][m][re,im] (Real, m contiguous) so
 // the x-pass reads whole rows and the stage kernel reads m-tiles.
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "rbc_internal.hpp"
 
@@ -1693,18 +1695,61 @@ hipError_t launch_set_meta(SlotMeta* meta, int slot, SlotMeta v, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const GridPlan& g, Work& w, const double* X, int slot0, int count, int cap, double* out,
-                       int ld, const SlotMeta* meta, int t, int stride, int nsf, int S, hipStream_t st) {
-  if (count < 1 || count > w.cap || slot0 < 0 || slot0 >= cap || (meta && stride < 1)) return hipErrorInvalidValue;
+size_t diag_partials_per_state(const GridDev& d) {
+  const int MC = diag_modes(d.Nz);
+  return size_t(4) * ((d.Mx + MC - 1) / MC);
+}
+
+hipError_t launch_diag_into(const GridPlan& g, double* part, const double* X, int slot0, int count, int cap,
+                            double* out, int ld, const SlotMeta* meta, int t, int stride, int nsf, int S,
+                            hipStream_t st) {
+  if (count < 1 || slot0 < 0 || slot0 >= cap || (meta && stride < 1)) return hipErrorInvalidValue;
   const int MC = diag_modes(g.dev.Nz), nchunk = (g.dev.Mx + MC - 1) / MC;
   const size_t lds = sizeof(double) * 8 * size_t(MC) * g.dev.Nz;
   hipLaunchKernelGGL(diag_partial_kernel, dim3(count * nchunk), dim3(kBlock), lds, st, g.dev, X, slot0, cap, nchunk,
-                     w.dpart);
+                     part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(diag_final_kernel, dim3(count), dim3(64), 0, st, g.dev, X, slot0, cap, nchunk,
-                     (const double*)w.dpart, out, ld, meta, t, stride, nsf, S);
+                     (const double*)part, out, ld, meta, t, stride, nsf, S);
   return hipGetLastError();
+}
+
+hipError_t launch_diag(const GridPlan& g, Work& w, const double* X, int slot0, int count, int cap, double* out,
+                       int ld, const SlotMeta* meta, int t, int stride, int nsf, int S, hipStream_t st) {
+  if (count > w.cap) return hipErrorInvalidValue;   // w.dpart holds w.cap states' partials
+  return launch_diag_into(g, w.dpart, X, slot0, count, cap, out, ld, meta, t, stride, nsf, S, st);
+}
+
+// ---------------------------------------------------- allocation-free scratch ---
+//
+// Device scratch of the allocation-free entry points: one array per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address hipGetSymbolAddress returns, taken
+// once per device with that device current (at handle creation).
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;   // per device id
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if (int(g_scratch_dev.size()) <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < int(g_scratch_dev.size())) ? g_scratch_dev[device] : nullptr;
 }
 
 hipError_t launch_restrict(const GridPlan& f, const GridPlan& c, const double* Xf, double* Xc, hipStream_t st) {

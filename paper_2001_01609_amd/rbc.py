@@ -102,6 +102,7 @@ def _load():
         "rbc_kernel_timing": (st, [vp, P(dbl), P(ctypes.c_int64), P(dbl)]),
         "rbc_synchronize": (st, [vp]),
         "rbc_get_pipeline_stats": (st, [vp, P(rbc_pipeline_stats)]),
+        "rbc_diagnostics_noalloc": (st, [vp, vp, i32, vp]),
         "rbc_get_state": (st, [vp, vp, P(ctypes.c_size_t)]),
         "rbc_set_state": (st, [vp, vp, ctypes.c_size_t]),
     }
@@ -230,6 +231,12 @@ def rbc_diagnostics(h, U, n_states: int) -> np.ndarray:
     _check(_lib.rbc_diagnostics(h, _ptr(U), n_states,
                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
     return out[:n_states]
+
+
+def rbc_diagnostics_noalloc(h, U, n_states: int, out) -> None:
+    """Records into the device tensor out ([n_states * RBC_DIAG] float64);
+    asynchronous, allocates nothing."""
+    _check(_lib.rbc_diagnostics_noalloc(h, _ptr(U), n_states, _ptr(out)), h)
 
 
 def rbc_fine_fp64_from(h) -> int:
