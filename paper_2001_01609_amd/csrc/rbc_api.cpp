@@ -106,6 +106,12 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
     return y + (y + u > v ? y + u : v);
   };
   while (g.MT > 2 && lds(g.MT) > 150 * 1024) g.MT = (g.MT == 6) ? 4 : g.MT / 2;
+  // Split path (the Chebyshev transforms as FP32 MFMA GEMMs over the whole
+  // batch): mixed-precision fine grids with Nz >= 128; RBC_SPLIT = 0 / 1
+  // overrides where the grid allows it (Nz >= 64, Nx >= 128, MT <= 4).
+  const bool split_ok = g.mixed && !coarse && g.Nz >= 64 && g.Mx % 64 == 0 && g.MT <= 4;
+  g.split = split_ok && g.Nz >= 128;
+  if (const char* e = std::getenv("RBC_SPLIT")) g.split = split_ok && std::atoi(e) != 0;
 }
 
 size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::GridPlan& c, int nsf, int nsc) {
@@ -195,6 +201,7 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes) {
     size_t n = g.Nz / 2, rb = g.mixed ? 4 : 8;
     size_t d = 2 * n * 14 + size_t(g.Mx) * 2 * (rbc::kFacT * n + 4) + size_t(g.Mx) * 2 * (rbc::kFacP * n + 4);
     size_t r = size_t(4) * (g.Pz / 2) * g.Nz + size_t(3) * g.Nz * (g.Pz / 2) + 2 * size_t(g.Px);
+    if (g.split) r += size_t(4) * (g.Pz / 2) * g.Nz + size_t(2) * g.Nz * (g.Pz / 2);   // maps by parity
     return d * 8 + r * rb + 16 * 256;
   };
   int nsf, nsc, sc;
@@ -205,6 +212,7 @@ rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes) {
   if (p->precision == RBC_MIXED && p->promote_fp64) {
     rbc::GridPlan f64 = f, c64 = c;
     f64.mixed = c64.mixed = false;
+    f64.split = c64.split = false;
     *device_bytes += tables(f64) + rbc::work_bytes(f64, cap) + tables(c64) + rbc::work_bytes(c64, 1);
   }
   return RBC_OK;
@@ -231,6 +239,7 @@ rbc_status rbc_create(const rbc_params* p, void* hip_stream, rbc_handle* out) {
     setup_grid(h->fine64, p, false, dtf);
     setup_grid(h->coarse64, p, true, dtc);
     h->fine64.mixed = h->coarse64.mixed = false;
+    h->fine64.split = h->coarse64.split = false;
     h->coarse64.one_xcd = false;
     e = rbc::build_plan(h->fine64);
     if (e.empty()) e = rbc::build_plan(h->coarse64);

@@ -28,6 +28,7 @@ constexpr int kDiagAvg = 9;       // time averages: Nu_V, Nu_b, Nu_t, Nu_int, KE
 // Fourier modes per block of the diagnostics kernel (Nz coefficients each).
 __host__ __device__ inline int diag_modes(int Nz) { return Nz >= 512 ? 1 : 512 / Nz; }
 constexpr int kBlock = 256;       // threads per block of the per-mode kernels
+constexpr int kChunkLanes = 32;   // lanes per system of the chunked band solves (more than 64 rows)
 constexpr int kXcds = 8;          // XCDs of the device; workgroup b runs on XCD b mod kXcds
 
 // Workgroups to launch for nwork work blocks (GridDev::one_xcd: kXcds per
@@ -51,7 +52,10 @@ struct GridDev {
   int Nx, Nz, Mx, Px, Pz, n;      // n = Nz / 2
   int nrT, nrP;                   // band rows per parity: n - 1 (T, u_bar), n - 2 (psi)
   int MT;                         // modes per block in the per-mode kernel
-  int ntile;                      // ceil(Mx / MT): mode tiles (mixed-space arrays are tile-major)
+  int ntile;                      // ceil(Mx / MT): tiles of the per-mode kernel
+  int XT, nxt;                    // mode tile of the mixed-space arrays (tile-major) and their count:
+                                  // XT = MT in the fused path, kGemmModes in the split path
+  int split;                      // 1: split path (transforms as FP32 MFMA GEMMs, see fwd_gemm_kernel)
   int state;                      // doubles per state = 4 Mx Nz
   double kscale;                  // k_m = m * kscale
   double nu, kappa, scale;        // viscosity, diffusivity, dzeta/dz = 2/Lz
@@ -72,6 +76,8 @@ struct GridDev {
   const void* Winv;               // Real [4][Pz/2][Nz]: d^q T_n / dz^q at Gauss points
   const void* Wfwd;               // Real [3][Nz][Pz/2]: folded forward maps (psi, T, u_bar rows)
   const void* tw;                 // Real2 [Px]: exp(-2 pi i t / Px)
+  const float* Winv2;             // split path: [4 q][2 p][Pz/2 j][Nz/2 i] = Winv[q][j][2 i + p]
+  const float* Wfwd2;             // split path: [2 f][2 p][Nz/2 i][Pz/2 j] = Wfwd[f][2 i + p][j]
   int nrad, rad[12];              // FFT radix plan for Px
 };
 
@@ -87,8 +93,13 @@ struct GridPlan {
   Tableau tab;
   int MT = 8;
   bool mixed = false;
+  // Split path (mixed precision, Nz >= 64, Nx >= 128): the forward and
+  // inverse Chebyshev transforms of a stage run as batched FP32 MFMA GEMMs
+  // over every column of the launch (fwd_gemm_kernel, inv_gemm_kernel)
+  // around the per-mode solve kernel, instead of inside it.
+  bool split = false;
   // host tables
-  std::vector<double> bS10, bD2, bA, bB, bD4, facT, facP, Winv, Wfwd, tw;
+  std::vector<double> bS10, bD2, bA, bB, bD4, facT, facP, Winv, Wfwd, tw, Winv2, Wfwd2;
   int facT_stride = 0, facP_stride = 0;
   double max_growth = 0;
   // device copies
@@ -111,7 +122,11 @@ struct Work {
   void* Ehist = nullptr;   // Real [s][cap][state]
   double* LYhist = nullptr;  // [s-1][cap][state]
   double* dpart = nullptr;   // [cap][mode chunks][4] diagnostic partial sums
+  float* Yf = nullptr;       // split path: [cap][field][m][re,im][parity][Nz/2] new stage (FP32)
 };
+// Modes per column group of the split path's GEMM kernels and the mode tile
+// of its mixed-space arrays.
+constexpr int kGemmModes = 32;
 size_t work_bytes(const GridPlan& g, int cap);
 hipError_t alloc_work(const GridPlan& g, int cap, Work& w);
 void free_work(Work& w);

@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
                                                         int slot0, int cap) {
   if (g.urgent) __builtin_amdgcn_s_setprio(3);
   extern __shared__ __align__(16) unsigned char smem[];
-  const int Pz = g.Pz, Mx = g.Mx, MT = g.MT, ntile = g.ntile;
+  const int Pz = g.Pz, Mx = g.Mx, MT = g.XT, ntile = g.nxt;   // mixed-space tiles
   const int ngrp = Pz / RB;
   const int bid = work_block(g.one_xcd);
   if (bid < 0) return;
@@ -561,6 +561,194 @@ __device__ __forceinline__ void solve_P_scan(double* __restrict__ v, int p, cons
 // Smallest power of two above n (segment width of the scan solves).
 constexpr int seg_width(int n) { return n < 4 ? 4 : (n < 8 ? 8 : (n < 16 ? 16 : (n < 32 ? 32 : 64))); }
 
+// Chunked scan form of the same bordered solves for systems longer than a
+// wavefront: W lanes per system, lane li owns the R consecutive band rows
+// [li R, li R + R) (R W >= NR).  Each elimination sweep composes the lane's
+// R affine maps in registers, combines the lanes' composites by a
+// Hillis-Steele scan over the W lanes (log2 W shuffle steps), and re-runs
+// its R rows from the incoming value: 2 R + log2 W dependent steps per
+// sweep instead of NR.  The re-run uses the sequential recurrences, so
+// only the chunk boundaries carry the scan's rounding.
+template <int NR, int W, int R>
+__device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, const double* __restrict__ fac,
+                                              double gbc, bool slope, int li) {
+  static_assert(W * R >= NR && W <= 64, "chunks must cover the system within one wavefront");
+  const int i0 = li * R;
+  double f[R], l[R], d[R], u[R], vc[R], x[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = i0 + q;
+    const bool act = i < NR;
+    const double* fr = fac + i * kFacT;
+    f[q] = act ? v[2 * i + p] : 0.0;
+    l[q] = act ? fr[0] : 0.0;   // l_0 = 0
+    d[q] = act ? fr[1] : 0.0;
+    u[q] = act ? fr[2] : 0.0;   // u_(NR-1) = 0
+    vc[q] = act ? fr[3] : 0.0;
+  }
+  // forward: y_i = -l_i y_(i-1) + f_i; rows beyond NR give y = 0
+  double A = 1.0, B = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    A = -l[q] * A;
+    B = f[q] - l[q] * B;
+  }
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double Ap = __shfl_up(A, o, W), Bp = __shfl_up(B, o, W);
+    if (li >= o) {
+      B = A * Bp + B;
+      A = A * Ap;
+    }
+  }
+  double y = __shfl_up(B, 1, W);
+  if (li == 0) y = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    y = f[q] - l[q] * y;
+    f[q] = y;   // f now holds y
+  }
+  // backward: x_i = (y_i - u_i x_(i+1)) d_i
+  A = 1.0;
+  B = 0.0;
+#pragma unroll
+  for (int q = R - 1; q >= 0; --q) {
+    B = -u[q] * d[q] * B + d[q] * f[q];
+    A = -u[q] * d[q] * A;
+  }
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double An = __shfl_down(A, o, W), Bn = __shfl_down(B, o, W);
+    if (li + o < W) {
+      B = A * Bn + B;
+      A = A * An;
+    }
+  }
+  double xn = __shfl_down(B, 1, W);
+  if (li == W - 1) xn = 0.0;
+  double part = 0.0;
+#pragma unroll
+  for (int q = R - 1; q >= 0; --q) {
+    xn = (f[q] - u[q] * xn) * d[q];
+    x[q] = xn;
+    if (i0 + q < NR) part += wall_w(i0 + q, p, slope) * xn;
+  }
+  const double sum = seg_sum<W>(part);
+  const double xh = fac[NR * kFacT] * (gbc - sum);
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = x[q] - vc[q] * xh;
+  if (li == 0) v[p] = xh;
+}
+
+template <int NR, int W, int R>
+__device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, const double* __restrict__ fac, int li) {
+  static_assert(W * R >= NR && W <= 64, "chunks must cover the system within one wavefront");
+  const int i0 = li * R;
+  double f[R], l1[R], l2[R], d[R], u1[R], u2[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = i0 + q;
+    const bool act = i < NR;
+    const double* fr = fac + i * kFacP;
+    f[q] = act ? v[2 * i + p] : 0.0;
+    l1[q] = act ? fr[0] : 0.0;
+    l2[q] = act ? fr[1] : 0.0;
+    d[q] = act ? fr[2] : 0.0;
+    u1[q] = act ? fr[3] : 0.0;
+    u2[q] = act ? fr[4] : 0.0;
+  }
+  // forward: (y_i, y_(i-1)) = [[-l1, -l2], [1, 0]] (y_(i-1), y_(i-2)) + (f_i, 0);
+  // the chunk's composite (M, c), rows beyond NR reset to zero
+  double m00 = 1.0, m01 = 0.0, m10 = 0.0, m11 = 1.0, c0 = 0.0, c1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const bool act = i0 + q < NR;
+    const double a00 = act ? -l1[q] : 0.0, a01 = act ? -l2[q] : 0.0, a10 = act ? 1.0 : 0.0;
+    const double n00 = a00 * m00 + a01 * m10, n01 = a00 * m01 + a01 * m11;
+    const double n10 = a10 * m00, n11 = a10 * m01;
+    const double d0 = a00 * c0 + a01 * c1 + f[q], d1 = a10 * c0;
+    m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+    c0 = d0; c1 = d1;
+  }
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double p00 = __shfl_up(m00, o, W), p01 = __shfl_up(m01, o, W);
+    const double p10 = __shfl_up(m10, o, W), p11 = __shfl_up(m11, o, W);
+    const double q0 = __shfl_up(c0, o, W), q1 = __shfl_up(c1, o, W);
+    if (li >= o) {   // this composite after the earlier one
+      const double n0 = m00 * q0 + m01 * q1 + c0, n1 = m10 * q0 + m11 * q1 + c1;
+      const double a00 = m00 * p00 + m01 * p10, a01 = m00 * p01 + m01 * p11;
+      const double a10 = m10 * p00 + m11 * p10, a11 = m10 * p01 + m11 * p11;
+      m00 = a00; m01 = a01; m10 = a10; m11 = a11;
+      c0 = n0; c1 = n1;
+    }
+  }
+  double y1 = __shfl_up(c0, 1, W), y2 = __shfl_up(c1, 1, W);
+  if (li == 0) y1 = y2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const double y = f[q] - l1[q] * y1 - l2[q] * y2;
+    y2 = y1;
+    y1 = y;
+    f[q] = y;   // f now holds y
+  }
+  // backward: (x_i, x_(i+1)) = [[-u1 d, -u2 d], [1, 0]] (x_(i+1), x_(i+2)) + (d y_i, 0)
+  m00 = 1.0; m01 = 0.0; m10 = 0.0; m11 = 1.0; c0 = 0.0; c1 = 0.0;
+#pragma unroll
+  for (int q = R - 1; q >= 0; --q) {
+    const bool act = i0 + q < NR;
+    const double a00 = act ? -u1[q] * d[q] : 0.0, a01 = act ? -u2[q] * d[q] : 0.0, a10 = act ? 1.0 : 0.0;
+    const double n00 = a00 * m00 + a01 * m10, n01 = a00 * m01 + a01 * m11;
+    const double n10 = a10 * m00, n11 = a10 * m01;
+    const double d0 = a00 * c0 + a01 * c1 + d[q] * f[q], d1 = a10 * c0;
+    m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+    c0 = d0; c1 = d1;
+  }
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const double p00 = __shfl_down(m00, o, W), p01 = __shfl_down(m01, o, W);
+    const double p10 = __shfl_down(m10, o, W), p11 = __shfl_down(m11, o, W);
+    const double q0 = __shfl_down(c0, o, W), q1 = __shfl_down(c1, o, W);
+    if (li + o < W) {   // this chunk's map after the later chunks' composite
+      const double n0 = m00 * q0 + m01 * q1 + c0, n1 = m10 * q0 + m11 * q1 + c1;
+      const double a00 = m00 * p00 + m01 * p10, a01 = m00 * p01 + m01 * p11;
+      const double a10 = m10 * p00 + m11 * p10, a11 = m10 * p01 + m11 * p11;
+      m00 = a00; m01 = a01; m10 = a10; m11 = a11;
+      c0 = n0; c1 = n1;
+    }
+  }
+  double x1 = __shfl_down(c0, 1, W), x2 = __shfl_down(c1, 1, W);
+  if (li == W - 1) x1 = x2 = 0.0;
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int q = R - 1; q >= 0; --q) {
+    const double xx = (f[q] - u1[q] * x1 - u2[q] * x2) * d[q];
+    x2 = x1;
+    x1 = xx;
+    f[q] = xx;   // f now holds x
+    if (i0 + q < NR) {
+      const double nn = double(2 * (i0 + q + 2) + p);
+      s0 += xx;
+      s1 += nn * nn * xx;
+    }
+  }
+  s0 = seg_sum<W>(s0);
+  s1 = seg_sum<W>(s1);
+  const double* si = fac + NR * kFacP;
+  const double h0 = -(si[0] * s0 + si[1] * s1);
+  const double h1 = -(si[2] * s0 + si[3] * s1);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = i0 + q;
+    if (i < NR) v[2 * (i + 2) + p] = f[q] - fac[i * kFacP + 5] * h0 - fac[i * kFacP + 6] * h1;
+  }
+  if (li == 0) {
+    v[p] = h0;
+    v[2 + p] = h1;
+  }
+}
+
 // Copies the factor blocks of modes m0..m0+MT-1 (both parities) into LDS,
 // eight loads in flight per thread.
 template <int MT>
@@ -616,12 +804,13 @@ struct StageLds {
   size_t sFT, sFP, total;
 };
 template <int NZ, int MT>
-__host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool pre) {
+__host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool pre, bool split = false) {
   constexpr size_t PZ = 3 * NZ / 2;
   const size_t tile = sizeof(double) * 4 * MT * (NZ + 1);
-  const size_t nh = rb * (4 * PZ * MT + PZ);
+  // products of the tile (fused path) or only the mean of u w (split path)
+  const size_t nh = split ? rb * PZ : rb * (4 * PZ * MT + PZ);
   // phase G scratch: only the two-pass inverse transform of two-mode tiles
-  const size_t vals = (MT <= 2) ? rb * PZ * MT * 12 : 0;
+  const size_t vals = (MT <= 2 && !split) ? rb * PZ * MT * 12 : 0;
   StageLds L{};
   if (!pre) {
     const size_t fac = sizeof(double) * size_t(MT) * 2 * size_t((fsT > fsP ? fsT : fsP) | 1);
@@ -649,11 +838,18 @@ __host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool 
 //   U   union { Real sN[2][PZ][2 MT] + sq[PZ];  double sF[2 MT][odd stride] }
 //   (latency variant: sN + sq, then the factor blocks of both equations in
 //   regions of their own; see stage_lds)
-template <typename Real, int NZ, int MT>
+//
+// Split path (SPLIT, mixed precision): the forward transform of the products
+// (phase B) and the inverse transform of the new stage (phase G) run as
+// batched GEMMs in fwd_gemm_kernel and inv_gemm_kernel.  Phase B then only
+// reads the explicit terms that fwd_gemm_kernel wrote to this stage's slot
+// of Ehist (and forms the mean-flow term of mode 0 from the mean of u w),
+// and phase G writes the new stage in FP32, split by parity, to Yf.
+template <typename Real, int NZ, int MT, bool SPLIT = false>
 __global__ void __launch_bounds__(kBlock)
 stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __restrict__ qbar,
              double* __restrict__ X, Real* __restrict__ Ehist, double* __restrict__ LYhist,
-             Real* __restrict__ Q, double* __restrict__ Eout) {
+             Real* __restrict__ Q, double* __restrict__ Eout, float* __restrict__ Yf) {
   constexpr int PZ = 3 * NZ / 2, PH = PZ / 2, LD = NZ + 1, NH = NZ / 2;
   constexpr int NRT = NH - 1, NRP = NH - 2;
   constexpr int NC = 4 * MT;                 // columns (field, mode, re/im)
@@ -685,8 +881,8 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   double* sX = sY + 4 * MT * LD;
   unsigned char* uni = reinterpret_cast<unsigned char*>(sX + 4 * MT * LD);
   Real* sN = reinterpret_cast<Real*>(uni);
-  Real* sq = sN + 4 * PZ * MT;
-  const StageLds Ls = stage_lds<NZ, MT>(sizeof(Real), g.facT_stride, g.facP_stride, kPre);
+  Real* sq = SPLIT ? sN : sN + 4 * PZ * MT;
+  const StageLds Ls = stage_lds<NZ, MT>(sizeof(Real), g.facT_stride, g.facP_stride, kPre, SPLIT);
   double* sFT = reinterpret_cast<double*>(smem + Ls.sFT);
   double* sFP = reinterpret_cast<double*>(smem + Ls.sFP);
   const int tid = threadIdx.x;
@@ -779,7 +975,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     // ---- phase A: products of this tile on the padded Gauss points (two
     // contiguous runs of PZ x 2 MT values in the mode-tile-major layout), and
     // the old state; eight loads in flight per thread
-    {
+    if constexpr (!SPLIT) {
       constexpr int U = 8;
       constexpr int half = PZ * 2 * MT, total = 2 * half;
       const size_t tq = size_t(PZ) * 2 * MT;
@@ -847,7 +1043,34 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     // ---- phase B: explicit terms of the previous stage on the band rows.
     // Item (f, row): one row of the folded forward map against every column
     // (mode, re/im) of the field; item f = 2 is the u_bar column of mode 0.
-    if constexpr (kWide) {
+    if constexpr (SPLIT) {
+      // the forward GEMM's result for this stage; the u_bar column of mode 0
+      // (whose slot holds no streamfunction) from the mean of u w
+      const Real* Ein = Ehist + (size_t(a.stage - 1) * a.cap + s) * st;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        if (c >= NC) continue;
+        const int f = fld(c), m = m0 + mtc(c);
+        if (m >= Mx || (f == 0 && m == 0)) continue;
+        if (r >= ((f == 0) ? NZ - 4 : NZ - 2)) continue;
+        const double E = double(Ein[goff(c) + r]);
+        if (a.mode == kModeExplicit)
+          Eout[goff(c) + r] = E;
+        else
+          sY[yoff(c) + r] = a.hae[a.stage - 1] * E;
+      }
+      if (m0 == 0)
+        for (int rr = tid; rr < NZ - 2; rr += kBlock) {
+          const Real* w = W + (size_t(2) * NZ + rr) * PH;
+          const Real sg = (rr & 1) ? Real(1) : Real(-1);
+          Real acc[2 * MT];
+          acc[0] = Real(0);
+#pragma unroll 8
+          for (int j = 0; j < PH; ++j) acc[0] += w[j] * (sq[j] + sg * sq[PZ - 1 - j]);
+          store_explicit(2, rr, acc);
+        }
+    } else if constexpr (kWide) {
       // two-mode tiles: each item split over JS lanes that take every JS-th
       // Gauss point, summed by shuffles
     constexpr int JS = 4;
@@ -986,7 +1209,22 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     // Two-mode tiles (latency-bound launches): scans with one lane per band
     // row up to 63 rows.  Wider tiles (throughput-bound batched launches,
     // where the other blocks' phases hide the sweep): one lane per system.
-    if constexpr (kWide && NRT < 64) {
+    if constexpr (NRT >= 64) {
+      // long systems: chunked scans, 32 lanes of four rows per system
+      for (int sys0 = 0; sys0 < 4 * MT; sys0 += kBlock / kChunkLanes) {
+        const int sys = sys0 + tid / kChunkLanes, li = tid % kChunkLanes;
+        if (sys < 4 * MT) {
+          const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
+          if (m < Mx) {
+            double gbc = 0.0;
+            if (m == 0 && ri == 0) gbc = g.bcT[p];
+            solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(
+                sY + ((MT + mt) * 2 + ri) * LD, p, sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc,
+                g.fluxT != 0, li);
+          }
+        }
+      }
+    } else if constexpr (kWide && NRT < 64) {
       constexpr int WS = seg_width(NRT);
       for (int sys0 = 0; sys0 < 4 * MT; sys0 += kBlock / WS) {
         const int sys = sys0 + tid / WS, li = tid % WS;
@@ -1029,7 +1267,22 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
     __syncthreads();
-    if constexpr (kWide && NRT < 64) {
+    if constexpr (NRT >= 64) {
+      for (int sys0 = 0; sys0 < 4 * MT; sys0 += kBlock / kChunkLanes) {
+        const int sys = sys0 + tid / kChunkLanes, li = tid % kChunkLanes;
+        if (sys < 4 * MT) {
+          const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
+          if (m < Mx) {
+            const double* fac = sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
+            double* v = sY + (mt * 2 + ri) * LD;
+            if (m == 0)
+              solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(v, p, fac, 0.0, false, li);
+            else
+              solve_P_chunk<NRP, kChunkLanes, (NRP + kChunkLanes - 1) / kChunkLanes>(v, p, fac, li);
+          }
+        }
+      }
+    } else if constexpr (kWide && NRT < 64) {
       constexpr int WS = seg_width(NRT);   // NRP < NRT: the same segments fit
       for (int sys0 = 0; sys0 < 4 * MT; sys0 += kBlock / WS) {
         const int sys = sys0 + tid / WS, li = tid % WS;
@@ -1101,6 +1354,17 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
     if (!a.do_zinv) return;
+  }
+  if constexpr (SPLIT) {
+    // ---- phase G (split path): the new stage in FP32 by parity, for the
+    // inverse GEMM
+    float* y = Yf + size_t(s) * st;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const int c = c0 + kc * CR;
+      if (c < NC && m0 + mtc(c) < Mx) y[goff(c) + (r & 1) * (NZ / 2) + (r >> 1)] = float(sY[yoff(c) + r]);
+    }
+    return;
   }
   // ---- phase G: values and z-derivatives of the new stage at the padded
   // Gauss points, six quantities per mode (m contiguous in HBM).
@@ -1265,6 +1529,256 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
   }
+  }
+}
+
+// ------------------------------------------------ split path: GEMM kernels ---
+//
+// The Chebyshev transforms of a stage as batched FP32 MFMA GEMMs over every
+// column (slice, mode, re/im) of the launch, so that each element of a
+// transform map, held in LDS, serves every column a block visits instead of
+// being streamed from L2 once per two-mode block.  Both kernels are
+// persistent over columns: a block loads its slab of the map once and loops
+// over column groups.  Even and odd Chebyshev coefficients are separate
+// reductions (the Gauss-point reflection halves every map).
+//
+// MFMA v_mfma_f32_16x16x4f32 (one 64-lane wavefront): lane l supplies
+// A[l % 16][k] and B[k][l % 16] for k = l / 16, and holds D[4 (l / 16) + r]
+// [l % 16], r = 0..3.  The reduction index of the four lane groups is
+// permuted consistently on both operands (group g takes k = 4 g + t at
+// instruction t of four), so that each lane's four operands of four
+// consecutive instructions are contiguous: one 16-byte load.
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int NZ>
+struct InvGemmShape {
+  static constexpr int NH = NZ / 2, PH = 3 * NZ / 4, PZ = 3 * NZ / 2;
+  static constexpr int JT = (PH % 32 == 0) ? 32 : 16;   // Gauss points per block
+  static constexpr int RT = JT / 16;                    // 16-row tiles per (q, parity)
+  static constexpr int LDA = NH + 4;                    // LDS row stride (floats): 4-bank shift per row
+  static constexpr int NJT = PH / JT;
+  static constexpr size_t lds = sizeof(float) * 4 * 2 * JT * LDA;
+};
+
+template <int NZ>
+struct FwdGemmShape {
+  static constexpr int NH = NZ / 2, PH = 3 * NZ / 4, PZ = 3 * NZ / 2;
+  static constexpr int RH = NH < 64 ? NH : 64;          // half-index rows per block (both parities)
+  static constexpr int NRH = NH / RH;
+  static constexpr int RT = RH / 16;
+  static constexpr int LDA = PH + 4;
+  static constexpr int CT = 2;                          // column tiles (8 modes x re/im) per wavefront
+  static constexpr int GM = 4 * 8 * CT;                 // modes per block and column group
+  static constexpr size_t lds = sizeof(float) * 2 * RH * LDA;
+};
+
+// Inverse transform of the new stage: for every column of Yf, values and
+// z-derivatives d^q/dz^q (q = 0..3 for psi / u_bar, 0..1 for T) at the
+// padded Gauss points, combined into the six mixed-space quantities u, w,
+// omega_x, omega_z, T_x, T_z of each mode and written to Q.  Block: one tile
+// of JT Gauss points j < Pz/2 (and, by reflection, Pz-1-j) and column groups
+// of kGemmModes modes of one state (each wavefront eight modes, re and im,
+// of both fields).
+template <int NZ>
+__global__ void __launch_bounds__(256)
+inv_gemm_kernel(GridDev g, const float* __restrict__ Yf, float* __restrict__ Q, int slot0, int cap, int count) {
+  using S = InvGemmShape<NZ>;
+  constexpr int NH = S::NH, PH = S::PH, PZ = S::PZ, JT = S::JT, RT = S::RT, LDA = S::LDA, NJT = S::NJT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* sA = reinterpret_cast<float*>(smem);   // [q][parity][JT][LDA]
+  const int jt = blockIdx.x % NJT, bi = blockIdx.x / NJT, nb = gridDim.x / NJT;
+  const int j0 = jt * JT;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 4 * 2 * JT * (NH / 4); e += 256) {
+    const int i4 = e % (NH / 4), row = e / (NH / 4);   // row = (q 2 + p) JT + jj
+    const int jj = row % JT, qp = row / JT;
+    const f32x4 v = *reinterpret_cast<const f32x4*>(g.Winv2 + (size_t(qp) * PH + j0 + jj) * NH + 4 * i4);
+    *reinterpret_cast<f32x4*>(sA + size_t(row) * LDA + 4 * i4) = v;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, lc = lane & 15, lg = lane >> 4;
+  const int Mx = g.Mx, st = g.state, XT = g.XT, nxt = g.nxt;
+  const int gps = Mx / kGemmModes;
+  const int ngroups = count * gps;
+  const size_t qs = size_t(nxt) * PZ * XT * 2;   // floats between quantities of one state
+  for (int cg = bi; cg < ngroups; cg += nb) {
+    const int b = cg / gps, mg = cg - b * gps;
+    const int s = ring_slot(b, slot0, cap);
+    const int m = mg * kGemmModes + wave * 8 + (lc >> 1), ri = lc & 1;
+    const float* yp = Yf + size_t(s) * st + size_t((0 * Mx + m) * 2 + ri) * NZ;
+    const float* yt = Yf + size_t(s) * st + size_t((1 * Mx + m) * 2 + ri) * NZ;
+    f32x4 aP[4][2][RT], aT[2][2][RT];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) aP[q][p][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) aT[q][p][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll 1
+      for (int kc = 0; kc < NH; kc += 16) {
+        const f32x4 bp = *reinterpret_cast<const f32x4*>(yp + p * NH + kc + 4 * lg);
+        const f32x4 bt = *reinterpret_cast<const f32x4*>(yt + p * NH + kc + 4 * lg);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 a =
+                *reinterpret_cast<const f32x4*>(sA + size_t((q * 2 + p) * JT + rt * 16 + lc) * LDA + kc + 4 * lg);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              aP[q][p][rt] = mfma_16x16x4(a[t], bp[t], aP[q][p][rt]);
+              if (q < 2) aT[q][p][rt] = mfma_16x16x4(a[t], bt[t], aT[q][p][rt]);
+            }
+          }
+      }
+    }
+    // six quantities of this lane's (mode, re/im) at j and Pz-1-j; the other
+    // half of the complex pair sits in the neighbouring lane
+    const float k = float(m * g.kscale), k2 = k * k;
+    const float sre = ri ? -1.f : 1.f;
+    const int tile = m / XT, mt = m - tile * XT;
+    float* qb = Q + size_t(s) * 6 * qs + size_t(tile) * PZ * XT * 2 + size_t(mt) * 2 + ri;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + rt * 16 + 4 * lg + r;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          // d^q T_n / dz^q at the reflected point is (-1)^(n+q) times that at j
+          float vP[4], vT[2];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float e0 = aP[q][0][rt][r], e1 = aP[q][1][rt][r];
+            vP[q] = side ? ((q & 1) ? e1 - e0 : e0 - e1) : e0 + e1;
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const float e0 = aT[q][0][rt][r], e1 = aT[q][1][rt][r];
+            vT[q] = side ? ((q & 1) ? e1 - e0 : e0 - e1) : e0 + e1;
+          }
+          const float om = vP[2] - k2 * vP[0];
+          const float xP0 = __shfl_xor(vP[0], 1, 64), xom = __shfl_xor(om, 1, 64), xT0 = __shfl_xor(vT[0], 1, 64);
+          float out[6];
+          if (m > 0) {
+            out[0] = vP[1];                    // u = psi_z
+            out[1] = sre * k * xP0;            // w = -i k psi
+            out[2] = -sre * k * xom;           // omega_x = i k omega
+            out[3] = vP[3] - k2 * vP[1];       // omega_z
+            out[4] = -sre * k * xT0;           // T_x = i k T
+            out[5] = vT[1];                    // T_z
+          } else {
+            out[0] = ri ? 0.f : vP[0];         // u = u_bar
+            out[1] = 0.f;
+            out[2] = 0.f;
+            out[3] = ri ? 0.f : vP[2];         // omega_z = u_bar_zz
+            out[4] = 0.f;
+            out[5] = ri ? 0.f : vT[1];
+          }
+          const int jj = side ? PZ - 1 - j : j;
+#pragma unroll
+          for (int qq = 0; qq < 6; ++qq) qb[qq * qs + size_t(jj) * XT * 2] = out[qq];
+        }
+      }
+  }
+}
+
+// Forward transform of the products: for every column (mode, re/im) of the
+// field f of each state, the explicit term -S F N on all rows n (the
+// equation basis folded into the map; rows beyond the band are not read),
+// written to this stage's slot of Ehist.  Block: field f, rows 2 i + p
+// for i in one RH-row half and both parities (so that a lane writes eight
+// consecutive coefficients), column groups of GM modes of one state.
+template <int NZ>
+__global__ void __launch_bounds__(256)
+fwd_gemm_kernel(GridDev g, const float* __restrict__ Nh, float* __restrict__ E, int slot0, int cap, int count) {
+  using S = FwdGemmShape<NZ>;
+  constexpr int NH = S::NH, PH = S::PH, PZ = S::PZ, RH = S::RH, NRH = S::NRH, RT = S::RT, LDA = S::LDA,
+                CT = S::CT, GM = S::GM;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* sA = reinterpret_cast<float*>(smem);   // [parity][RH][LDA]
+  const int fh = blockIdx.x % (2 * NRH), bi = blockIdx.x / (2 * NRH), nb = gridDim.x / (2 * NRH);
+  const int f = fh / NRH, h = fh - f * NRH;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * RH * (PH / 4); e += 256) {
+    const int j4 = e % (PH / 4), row = e / (PH / 4);   // row = p RH + ii
+    const int ii = row % RH, p = row / RH;
+    const f32x4 v = *reinterpret_cast<const f32x4*>(g.Wfwd2 + ((size_t(f) * 2 + p) * NH + h * RH + ii) * PH + 4 * j4);
+    *reinterpret_cast<f32x4*>(sA + size_t(row) * LDA + 4 * j4) = v;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, lc = lane & 15, lg = lane >> 4;
+  const int Mx = g.Mx, st = g.state, XT = g.XT, nxt = g.nxt;
+  const int gps = Mx / GM;
+  const int ngroups = count * gps;
+  const int rs = XT * 2;   // floats between Gauss points in a mixed-space tile
+  for (int cg = bi; cg < ngroups; cg += nb) {
+    const int b = cg / gps, mg = cg - b * gps;
+    const int s = ring_slot(b, slot0, cap);
+    const float* nc[CT];
+    int mm[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int m = mg * GM + wave * (8 * CT) + ct * 8 + (lc >> 1);
+      const int tile = m / XT, mt = m - tile * XT;
+      mm[ct] = m;
+      nc[ct] = Nh + ((size_t(s) * 2 + f) * nxt + tile) * PZ * XT * 2 + mt * 2 + (lc & 1);
+    }
+    f32x4 acc[2][RT][CT];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[p][rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int kc = 0; kc < PH; kc += 16) {
+      float bs[CT][4], bd[CT][4];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int j = kc + 4 * lg + t;
+          const float n0 = nc[ct][size_t(j) * rs], n1 = nc[ct][size_t(PZ - 1 - j) * rs];
+          bs[ct][t] = n0 + n1;   // even rows: the value at Pz-1-j enters with +1
+          bd[ct][t] = n0 - n1;   // odd rows: with -1
+        }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const f32x4 a = *reinterpret_cast<const f32x4*>(sA + size_t(p * RH + rt * 16 + lc) * LDA + kc + 4 * lg);
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[p][rt][ct] = mfma_16x16x4(a[t], p ? bd[ct][t] : bs[ct][t], acc[p][rt][ct]);
+        }
+    }
+    // lane: rows i = h RH + 16 rt + 4 lg + r of both parities = coefficients
+    // n = 2 i + p, eight consecutive ones per (rt, ct)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      float* eo = E + size_t(s) * st + size_t((f * Mx + mm[ct]) * 2 + (lc & 1)) * NZ;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int n0 = 2 * (h * RH + rt * 16 + 4 * lg);
+        const f32x4 lo = {acc[0][rt][ct][0], acc[1][rt][ct][0], acc[0][rt][ct][1], acc[1][rt][ct][1]};
+        const f32x4 hi = {acc[0][rt][ct][2], acc[1][rt][ct][2], acc[0][rt][ct][3], acc[1][rt][ct][3]};
+        *reinterpret_cast<f32x4*>(eo + n0) = lo;
+        *reinterpret_cast<f32x4*>(eo + n0 + 4) = hi;
+      }
+    }
   }
 }
 
@@ -1503,27 +2017,80 @@ __global__ void defect_kernel(const double* __restrict__ part, int first, int la
 
 namespace {
 
-template <typename Real, int NZ, int MT>
+template <typename Real, int NZ, int MT, bool SPLIT = false>
 hipError_t run_stage_t(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
                        hipStream_t st) {
   const GridDev& d = g.dev;
   const int ntile = (d.Mx + MT - 1) / MT;
   constexpr bool pre = MT <= 2 && NZ <= 64;   // as in the kernel
-  const size_t lds = stage_lds<NZ, MT>(sizeof(Real), d.facT_stride, d.facP_stride, pre).total;
-  hipLaunchKernelGGL((stage_kernel<Real, NZ, MT>), dim3(xcd_grid(d.one_xcd, n_slices * ntile)), dim3(kBlock), lds, st,
-                     d, a,
-                     (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q, Eout);
+  const size_t lds = stage_lds<NZ, MT>(sizeof(Real), d.facT_stride, d.facP_stride, pre, SPLIT).total;
+  hipLaunchKernelGGL((stage_kernel<Real, NZ, MT, SPLIT>), dim3(xcd_grid(d.one_xcd, n_slices * ntile)), dim3(kBlock),
+                     lds, st, d, a, (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q,
+                     Eout, w.Yf);
   return hipGetLastError();
 }
 
 template <typename Real, int NZ>
 hipError_t run_stage_nz(const GridPlan& g, Work& w, const StageArgs& a, double* X, int n_slices, double* Eout,
                         hipStream_t st) {
+  if constexpr (sizeof(Real) == 4 && NZ >= 64) {
+    if (g.split) {
+      switch (g.dev.MT) {
+        case 2: return run_stage_t<Real, NZ, 2, true>(g, w, a, X, n_slices, Eout, st);
+        case 4: return run_stage_t<Real, NZ, 4, true>(g, w, a, X, n_slices, Eout, st);
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  if (g.split) return hipErrorInvalidValue;
   switch (g.dev.MT) {
     case 2: return run_stage_t<Real, NZ, 2>(g, w, a, X, n_slices, Eout, st);
     case 4: return run_stage_t<Real, NZ, 4>(g, w, a, X, n_slices, Eout, st);
     case 6: return run_stage_t<Real, NZ, 6>(g, w, a, X, n_slices, Eout, st);
     case 8: return run_stage_t<Real, NZ, 8>(g, w, a, X, n_slices, Eout, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Persistent grid of a GEMM kernel: `parts` map slabs, each with as many
+// blocks as fit on the device next to the others (by LDS), at most one per
+// column group.
+inline int gemm_blocks(int parts, size_t lds, int ngroups) {
+  int per_cu = int((160 * 1024) / (lds ? lds : 1));
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  int nb = (256 * per_cu) / parts;
+  if (nb > ngroups) nb = ngroups;
+  if (nb < 1) nb = 1;
+  return parts * nb;
+}
+
+template <int NZ>
+hipError_t run_fwd_gemm_t(const GridPlan& g, Work& w, int stage, int slot0, int count, hipStream_t st) {
+  using S = FwdGemmShape<NZ>;
+  const int ngroups = count * (g.dev.Mx / S::GM);
+  float* E = static_cast<float*>(w.Ehist) + size_t(stage - 1) * w.cap * g.dev.state;
+  hipLaunchKernelGGL((fwd_gemm_kernel<NZ>), dim3(gemm_blocks(2 * S::NRH, S::lds, ngroups)), dim3(256), S::lds, st,
+                     g.dev, (const float*)w.Nh, E, slot0, w.cap, count);
+  return hipGetLastError();
+}
+
+template <int NZ>
+hipError_t run_inv_gemm_t(const GridPlan& g, Work& w, int slot0, int count, hipStream_t st) {
+  using S = InvGemmShape<NZ>;
+  const int ngroups = count * (g.dev.Mx / kGemmModes);
+  hipLaunchKernelGGL((inv_gemm_kernel<NZ>), dim3(gemm_blocks(S::NJT, S::lds, ngroups)), dim3(256), S::lds, st,
+                     g.dev, (const float*)w.Yf, (float*)w.Q, slot0, w.cap, count);
+  return hipGetLastError();
+}
+
+// The split path's transforms: forward (products of `stage` into its Ehist
+// slot) or inverse (Yf to the mixed-space quantities).
+hipError_t run_gemm(const GridPlan& g, Work& w, bool forward, int stage, int slot0, int count, hipStream_t st) {
+  if (!g.split) return hipErrorInvalidValue;
+  switch (g.dev.Nz) {
+    case 64: return forward ? run_fwd_gemm_t<64>(g, w, stage, slot0, count, st) : run_inv_gemm_t<64>(g, w, slot0, count, st);
+    case 128: return forward ? run_fwd_gemm_t<128>(g, w, stage, slot0, count, st) : run_inv_gemm_t<128>(g, w, slot0, count, st);
+    case 256: return forward ? run_fwd_gemm_t<256>(g, w, stage, slot0, count, st) : run_inv_gemm_t<256>(g, w, slot0, count, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1600,6 +2167,7 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, const StepRange& r,
                       int nu_ld, hipStream_t st, KernelTiming* tm) {
   const Tableau& tb = g.tab;
   hipError_t e;
+  const bool split = g.split;
   if (r.step0 == 0) {
     StageArgs a{};
     a.mode = kModeZinv;
@@ -1608,6 +2176,7 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, const StepRange& r,
     a.slot0 = r.slot0;
     a.s = tb.s;
     if ((e = run_stage<Real>(g, w, a, X, r.count, nullptr, st)) != hipSuccess) return e;
+    if (split && (e = run_gemm(g, w, false, 0, r.slot0, r.count, st)) != hipSuccess) return e;
   }
   for (int step = r.step0; step < r.step1; ++step) {
     const bool last = (step == r.n_total - 1);
@@ -1631,9 +2200,14 @@ hipError_t steps_impl(const GridPlan& g, Work& w, double* X, const StepRange& r,
       for (int j = 0; j < i; ++j) b.hae[j] = g.dt * tb.ae[i][j];
       for (int j = 1; j <= i; ++j) b.hai[j] = g.dt * tb.ai[i][j];
       b.haii = g.dt * tb.ai[i][i];
+      // split path: the forward GEMM, the per-mode solve kernel and (unless
+      // this is the run's last stage) the inverse GEMM; kernel 0 of the
+      // timing brackets all three
       if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
       if (timed) tm->units += r.count;
+      if (split && (e = run_gemm(g, w, true, i, r.slot0, r.count, st)) != hipSuccess) return e;
       if ((e = run_stage<Real>(g, w, b, X, r.count, nullptr, st)) != hipSuccess) return e;
+      if (split && b.do_zinv && (e = run_gemm(g, w, false, i, r.slot0, r.count, st)) != hipSuccess) return e;
       if (timed && tm->kernel == 0 && (e = timing_mark(tm, st)) != hipSuccess) return e;
     }
     if (nu_out && nu_stride > 0 && (step + 1) % nu_stride == 0) {
@@ -1676,11 +2250,14 @@ hipError_t launch_explicit(const GridPlan& g, Work& w, const double* X, double* 
   a.do_zinv = 1;
   a.cap = w.cap;
   a.s = g.tab.s;
+  a.stage = 1;   // the split path's forward GEMM writes the first Ehist slot
   hipError_t e;
   double* Xm = const_cast<double*>(X);
   if (g.mixed) {
     if ((e = run_stage<float>(g, w, a, Xm, 1, nullptr, st)) != hipSuccess) return e;
+    if (g.split && (e = run_gemm(g, w, false, 0, 0, 1, st)) != hipSuccess) return e;
     if ((e = run_xpass<float>(g, w, 0, 1, st)) != hipSuccess) return e;
+    if (g.split && (e = run_gemm(g, w, true, 1, 0, 1, st)) != hipSuccess) return e;
     a.mode = kModeExplicit;
     return run_stage<float>(g, w, a, Xm, 1, E, st);
   }

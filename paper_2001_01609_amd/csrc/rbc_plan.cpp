@@ -344,6 +344,25 @@ std::string build_plan(GridPlan& g) {
           g.Wfwd[(size_t(e) * N + r) * Ph + j] = -v;
         }
   }
+  // Split path: the same maps by parity for the GEMM kernels (FP32 rows of
+  // contiguous reduction index).
+  g.Winv2.clear();
+  g.Wfwd2.clear();
+  if (g.split) {
+    const int Nh = N / 2;
+    g.Winv2.assign(size_t(4) * 2 * Ph * Nh, 0.0);
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < 2; ++p)
+        for (int j = 0; j < Ph; ++j)
+          for (int i = 0; i < Nh; ++i)
+            g.Winv2[((size_t(q) * 2 + p) * Ph + j) * Nh + i] = g.Winv[(size_t(q) * Ph + j) * N + 2 * i + p];
+    g.Wfwd2.assign(size_t(2) * 2 * Nh * Ph, 0.0);
+    for (int f = 0; f < 2; ++f)
+      for (int p = 0; p < 2; ++p)
+        for (int i = 0; i < Nh; ++i)
+          for (int j = 0; j < Ph; ++j)
+            g.Wfwd2[((size_t(f) * 2 + p) * Nh + i) * Ph + j] = g.Wfwd[(size_t(f) * N + 2 * i + p) * Ph + j];
+  }
   // FFT twiddles and radix plan for Px = 3 * 2^q
   g.tw.assign(size_t(2) * g.Px, 0.0);
   for (int t = 0; t < g.Px; ++t) {
@@ -367,7 +386,7 @@ size_t plan_device_bytes(const GridPlan& g) {
   size_t rb = g.mixed ? 4 : 8;
   size_t d = g.bS10.size() + g.bD2.size() + g.bA.size() + g.bB.size() + g.bD4.size() +
              g.facT.size() + g.facP.size();
-  size_t r = g.Winv.size() + g.Wfwd.size() + g.tw.size();
+  size_t r = g.Winv.size() + g.Wfwd.size() + g.tw.size() + g.Winv2.size() + g.Wfwd2.size();
   return d * 8 + r * rb + 64 * 16;
 }
 
@@ -375,7 +394,7 @@ hipError_t upload_plan(GridPlan& g) {
   const bool mx = g.mixed;
   const size_t rb = mx ? 4 : 8;
   std::vector<const std::vector<double>*> dbl = {&g.bS10, &g.bD2, &g.bA, &g.bB, &g.bD4, &g.facT, &g.facP};
-  std::vector<const std::vector<double>*> rl = {&g.Winv, &g.Wfwd, &g.tw};
+  std::vector<const std::vector<double>*> rl = {&g.Winv, &g.Wfwd, &g.tw, &g.Winv2, &g.Wfwd2};
   size_t off = 0;
   std::vector<size_t> offs;
   auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -401,6 +420,9 @@ hipError_t upload_plan(GridPlan& g) {
   d.Nx = g.Nx; d.Nz = g.Nz; d.Mx = g.Mx; d.Px = g.Px; d.Pz = g.Pz; d.n = g.Nz / 2;
   d.nrT = d.n - 1; d.nrP = d.n - 2; d.MT = g.MT;
   d.ntile = (g.Mx + g.MT - 1) / g.MT;
+  d.split = g.split ? 1 : 0;
+  d.XT = g.split ? kGemmModes : g.MT;
+  d.nxt = (g.Mx + d.XT - 1) / d.XT;
   d.state = 4 * g.Mx * g.Nz;
   d.kscale = 2.0 * M_PI / g.Lx;
   d.nu = g.nu; d.kappa = g.kappa; d.scale = g.scale; d.Lz = g.Lz;
@@ -425,11 +447,16 @@ hipError_t upload_plan(GridPlan& g) {
   d.Winv = base + offs[7];
   d.Wfwd = base + offs[8];
   d.tw = base + offs[9];
+  d.Winv2 = g.split ? reinterpret_cast<const float*>(base + offs[10]) : nullptr;
+  d.Wfwd2 = g.split ? reinterpret_cast<const float*>(base + offs[11]) : nullptr;
   return hipSuccess;
 }
 
-// Modes rounded up to whole tiles (the mixed-space arrays are tile-major).
-static size_t padded_modes(const GridPlan& g) { return size_t((g.Mx + g.MT - 1) / g.MT) * g.MT; }
+// Modes rounded up to whole tiles of the mixed-space arrays (tile-major).
+static size_t padded_modes(const GridPlan& g) {
+  const int xt = g.split ? kGemmModes : g.MT;
+  return size_t((g.Mx + xt - 1) / xt) * xt;
+}
 
 size_t work_bytes(const GridPlan& g, int cap) {
   size_t rb = g.mixed ? 4 : 8;
@@ -439,7 +466,8 @@ size_t work_bytes(const GridPlan& g, int cap) {
   size_t eh = size_t(g.tab.s) * cap * st * rb;
   size_t ly = size_t(g.tab.s - 1) * cap * st * 8;
   size_t dp = size_t(cap) * ((g.Mx + diag_modes(g.Nz) - 1) / diag_modes(g.Nz)) * 4 * 8;
-  return q + nh + eh + ly + dp + 5 * 256;
+  size_t yf = g.split ? size_t(cap) * st * 4 : 0;
+  return q + nh + eh + ly + dp + yf + 6 * 256;
 }
 
 hipError_t alloc_work(const GridPlan& g, int cap, Work& w) {
@@ -454,6 +482,7 @@ hipError_t alloc_work(const GridPlan& g, int cap, Work& w) {
   if ((e = hipMalloc((void**)&w.LYhist, size_t(g.tab.s - 1) * cap * st * 8)) != hipSuccess) return e;
   const size_t nchunk = (g.Mx + diag_modes(g.Nz) - 1) / diag_modes(g.Nz);
   if ((e = hipMalloc((void**)&w.dpart, size_t(cap) * nchunk * 4 * 8)) != hipSuccess) return e;
+  if (g.split && (e = hipMalloc((void**)&w.Yf, size_t(cap) * st * 4)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -464,6 +493,7 @@ void free_work(Work& w) {
   if (w.Ehist) (void)hipFree(w.Ehist);
   if (w.LYhist) (void)hipFree(w.LYhist);
   if (w.dpart) (void)hipFree(w.dpart);
+  if (w.Yf) (void)hipFree(w.Yf);
   w = Work{};
 }
 

@@ -248,6 +248,61 @@ def test_slice_alone_equals_slice_in_batch_bitwise():
     assert np.array_equal(a, b)
 
 
+# ------------------------------------------------------ split fine path ---
+# The Chebyshev transforms as batched FP32 MFMA GEMMs around the per-mode
+# solve kernel (the default for mixed precision at Nz >= 128; RBC_SPLIT=1
+# forces it on smaller eligible grids).
+
+@pytest.mark.parametrize("Nx,Nz", [(128, 64), (128, 128), (128, 256)])
+def test_split_explicit_terms_match_oracle(Nx, Nz, monkeypatch):
+    monkeypatch.setenv("RBC_SPLIT", "1")
+    p = params(Nx, Nz, Ra=1e6, dt=2e-4, mixed=True)
+    case(f"split explicit {Nx}x{Nz}")
+    g = grid(p)
+    X = developed_state(g, 3)
+    h = create(p)
+    try:
+        U = to_dev(X.pack())
+        E = torch.zeros_like(U)
+        R().rbc_explicit_terms(h, U, E)
+        torch.cuda.synchronize()
+        got = E.cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    ref = O.Stepper(g).explicit(X).pack()
+    m = band_mask(g)
+    assert not got[~m].any()
+    ref[~m] = 0.0
+    assert_blocks(got, ref, g, 1e-5, "split explicit terms")
+
+
+@pytest.mark.parametrize("Nx,Nz,S", [(128, 64, 3), (256, 128, 2)])
+def test_split_steps_match_oracle_and_batch_invariance(Nx, Nz, S, monkeypatch):
+    """Several slices of developed flow, 8 steps on the split path: each
+    slice against the oracle per block (mixed bar), and the last slice
+    stepped alone equals itself in the batch, bit for bit."""
+    monkeypatch.setenv("RBC_SPLIT", "1")
+    p = params(Nx, Nz, Ra=1e6, dt=2e-4, mixed=True, S=S)
+    case(f"split steps {Nx}x{Nz} {S} slices")
+    g = grid(p)
+    Xs = [developed_state(g, 60 + i) for i in range(S)]
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        R().rbc_fine_step_batch(h, U, U, S, 8)
+        V = to_dev(Xs[-1].pack())
+        R().rbc_fine_step_batch(h, V, V, 1, 8)
+        torch.cuda.synchronize()
+        got = U.cpu().numpy().reshape(S, -1)
+        alone = V.cpu().numpy()
+    finally:
+        R().rbc_destroy(h)
+    assert np.array_equal(got[-1], alone)
+    st = O.Stepper(g)
+    for i, X in enumerate(Xs):
+        assert_blocks(got[i], st.run(X, 8).pack(), g, MIXED_TOL, f"split slice {i}", dev_T0=True)
+
+
 def _tiny_parareal_params(mixed=False):
     return params(32, 16, Ra=3e3, dt=0.02, scheme=4, mixed=mixed, S=4, Nx_c=16, Nz_c=8, t_end=2.0,
                   dt_c=0.05)

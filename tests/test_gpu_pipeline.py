@@ -76,6 +76,10 @@ CASES = {
     # statistics-based stop
     "stat_stop": dict(p=dict(Nx=32, Nz=16, Nx_c=16, Nz_c=8, S=6, dt=0.02, dt_c=0.05, t_end=3.0, mixed=True,
                              nu_stride=5, stat_tol=0.05), k_max=6, tol=1e-14),
+    # split fine path (the transforms as batched GEMMs over the ring's
+    # slots, which wrap), mixed with the FP64 switch
+    "split_ring": dict(p=dict(Nx=128, Nz=64, Nx_c=32, Nz_c=16, S=5, dt=0.01, dt_c=0.04, t_end=1.0, mixed=True,
+                              nu_stride=4), k_max=5, tol=1e-14, env={"RBC_SPLIT": "1"}),
     # prediction only
     "k0": dict(p=dict(Nx=32, Nz=16, Nx_c=16, Nz_c=8, S=4, dt=0.02, dt_c=0.05, t_end=2.0, mixed=False,
                       nu_stride=5), k_max=0, tol=0.0),
@@ -83,8 +87,10 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_pipelined_equals_sweep_then_batch_bitwise(name):
+def test_pipelined_equals_sweep_then_batch_bitwise(name, monkeypatch):
     c = CASES[name]
+    for k, v in c.get("env", {}).items():
+        monkeypatch.setenv(k, v)
     case(f"pipelined vs sweep-then-batch: {name}")
     p = params(**c["p"])
     g = O.Grid(p.Ra, p.Pr, p.Lx, p.Lz, p.Nx, p.Nz, p.dt_f)
