@@ -209,7 +209,7 @@ __device__ __forceinline__ Real wave_sum(Real v) {
 // in the second spectrum's place.
 template <typename Real, int PX, int RB>
 constexpr int xpass_spectra() {
-  return (sizeof(Real) == 8 && PX <= 768 && RB > 1) ? 2 : 3;
+  return ((sizeof(Real) == 8 && PX <= 768 && RB > 1) || (sizeof(Real) == 4 && PX >= 1536)) ? 2 : 3;
 }
 
 // One block of RB wavefronts per (slice, group of RB padded z points); wave w
@@ -804,9 +804,16 @@ struct StageLds {
   size_t sFT, sFP, total;
 };
 template <int NZ, int MT>
-__host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool pre, bool split = false) {
+__host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool pre, bool split = false,
+                                              bool lean = false) {
   constexpr size_t PZ = 3 * NZ / 2;
   const size_t tile = sizeof(double) * 4 * MT * (NZ + 1);
+  if (lean) {   // right-hand sides and the mean of u w only
+    StageLds L{};
+    L.sFT = L.sFP = 0;
+    L.total = tile + rb * PZ;
+    return L;
+  }
   // products of the tile (fused path) or only the mean of u w (split path)
   const size_t nh = split ? rb * PZ : rb * (4 * PZ * MT + PZ);
   // phase G scratch: only the two-pass inverse transform of two-mode tiles
@@ -866,6 +873,11 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   // memory: staged in LDS they cost more at entry and in bank conflicts than
   // their cached loads.)
   constexpr bool kPre = kWide && NZ <= 64;
+  // Lean variant of the split path for long systems (chunked solves): the
+  // old state and the band factors are read from global memory where they
+  // are used instead of being staged in LDS, so that four times as many
+  // blocks fit a compute unit (the solves are latency-bound).
+  constexpr bool kLean = SPLIT && NRT >= 64;
   static_assert(kBlock % NZ == 0, "NZ must divide the block size");
   if (g.urgent) __builtin_amdgcn_s_setprio(3);
   extern __shared__ __align__(16) unsigned char smem[];
@@ -878,11 +890,11 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   const int m0 = tile * MT;
   const int st = g.state;
   double* sY = reinterpret_cast<double*>(smem);
-  double* sX = sY + 4 * MT * LD;
-  unsigned char* uni = reinterpret_cast<unsigned char*>(sX + 4 * MT * LD);
+  double* sX = sY + 4 * MT * LD;   // not used by the lean variant
+  unsigned char* uni = reinterpret_cast<unsigned char*>(kLean ? sX : sX + 4 * MT * LD);
   Real* sN = reinterpret_cast<Real*>(uni);
   Real* sq = SPLIT ? sN : sN + 4 * PZ * MT;
-  const StageLds Ls = stage_lds<NZ, MT>(sizeof(Real), g.facT_stride, g.facP_stride, kPre, SPLIT);
+  const StageLds Ls = stage_lds<NZ, MT>(sizeof(Real), g.facT_stride, g.facP_stride, kPre, SPLIT, kLean);
   double* sFT = reinterpret_cast<double*>(smem + Ls.sFT);
   double* sFP = reinterpret_cast<double*>(smem + Ls.sFP);
   const int tid = threadIdx.x;
@@ -997,7 +1009,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     }
     if (m0 == 0)
       for (int j = tid; j < PZ; j += kBlock) sq[j] = qbar[size_t(s) * PZ + j];
-    if (a.mode == kModeStage) {
+    if (a.mode == kModeStage && !kLean) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
@@ -1151,7 +1163,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     if (a.mode == kModeExplicit) return;
     __syncthreads();
     // temperature factors into the (now free) union region
-    if constexpr (!kPre) stage_factors<MT>(sFT, g.facT, g.facT_stride, m0, Mx);
+    if constexpr (!kPre && !kLean) stage_factors<MT>(sFT, g.facT, g.facT_stride, m0, Mx);
     // ---- phase C: right-hand side of stage i on this thread's row
     const RowTables tb = kPre ? tbp : load_row_tables(g, r);
     {
@@ -1165,7 +1177,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (m >= Mx) continue;
         const bool psi = (f == 0 && m > 0);
         if (r >= (psi ? NZ - 4 : NZ - 2)) continue;
-        const double* xv = sX + yoff(c);
+        const double* xv = kLean ? Xs + goff(c) : sX + yoff(c);
         double MX;
         if (!psi) {
           MX = tb.s10[0] * xv[r] + tb.s10[1] * xv[r + 2] + (r + 4 < NZ ? tb.s10[2] * xv[r + 4] : 0.0);
@@ -1218,9 +1230,10 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           if (m < Mx) {
             double gbc = 0.0;
             if (m == 0 && ri == 0) gbc = g.bcT[p];
+            const double* fac = kLean ? g.facT + (size_t(m) * 2 + p) * g.facT_stride
+                                      : sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride);
             solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(
-                sY + ((MT + mt) * 2 + ri) * LD, p, sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride), gbc,
-                g.fluxT != 0, li);
+                sY + ((MT + mt) * 2 + ri) * LD, p, fac, gbc, g.fluxT != 0, li);
           }
         }
       }
@@ -1249,7 +1262,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     }
     __syncthreads();
     // flow factors; implicit buoyancy of the new temperature into psi
-    if constexpr (!kPre) stage_factors<MT>(sFP, g.facP, g.facP_stride, m0, Mx);
+    if constexpr (!kPre && !kLean) stage_factors<MT>(sFP, g.facP, g.facP_stride, m0, Mx);
     if (r < NZ - 4) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
@@ -1273,7 +1286,8 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (sys < 4 * MT) {
           const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
           if (m < Mx) {
-            const double* fac = sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
+            const double* fac = kLean ? g.facP + (size_t(m) * 2 + p) * g.facP_stride
+                                      : sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
             double* v = sY + (mt * 2 + ri) * LD;
             if (m == 0)
               solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(v, p, fac, 0.0, false, li);
@@ -1622,12 +1636,19 @@ inv_gemm_kernel(GridDev g, const float* __restrict__ Yf, float* __restrict__ Q, 
 #pragma unroll
         for (int q = 0; q < 2; ++q) aT[q][p][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
+    // the column operands of the next 16-coefficient chunk are loaded while
+    // the current one is multiplied (one wavefront per SIMD: nothing else
+    // hides the load latency)
+    f32x4 bpn = *reinterpret_cast<const f32x4*>(yp + 4 * lg);
+    f32x4 btn = *reinterpret_cast<const f32x4*>(yt + 4 * lg);
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
 #pragma unroll 1
       for (int kc = 0; kc < NH; kc += 16) {
-        const f32x4 bp = *reinterpret_cast<const f32x4*>(yp + p * NH + kc + 4 * lg);
-        const f32x4 bt = *reinterpret_cast<const f32x4*>(yt + p * NH + kc + 4 * lg);
+        const f32x4 bp = bpn, bt = btn;
+        const int nxt_off = (kc + 16 < NH) ? p * NH + kc + 16 : (p == 0 ? NH : p * NH + kc);
+        bpn = *reinterpret_cast<const f32x4*>(yp + nxt_off + 4 * lg);
+        btn = *reinterpret_cast<const f32x4*>(yt + nxt_off + 4 * lg);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -1741,6 +1762,17 @@ fwd_gemm_kernel(GridDev g, const float* __restrict__ Nh, float* __restrict__ E, 
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[p][rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // products of the next 16 Gauss points are loaded while the current
+    // ones are multiplied
+    float n0n[CT][4], n1n[CT][4];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = 4 * lg + t;
+        n0n[ct][t] = nc[ct][size_t(j) * rs];
+        n1n[ct][t] = nc[ct][size_t(PZ - 1 - j) * rs];
+      }
 #pragma unroll 1
     for (int kc = 0; kc < PH; kc += 16) {
       float bs[CT][4], bd[CT][4];
@@ -1748,10 +1780,17 @@ fwd_gemm_kernel(GridDev g, const float* __restrict__ Nh, float* __restrict__ E, 
       for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const int j = kc + 4 * lg + t;
-          const float n0 = nc[ct][size_t(j) * rs], n1 = nc[ct][size_t(PZ - 1 - j) * rs];
-          bs[ct][t] = n0 + n1;   // even rows: the value at Pz-1-j enters with +1
-          bd[ct][t] = n0 - n1;   // odd rows: with -1
+          bs[ct][t] = n0n[ct][t] + n1n[ct][t];   // even rows: the value at Pz-1-j enters with +1
+          bd[ct][t] = n0n[ct][t] - n1n[ct][t];   // odd rows: with -1
+        }
+      const int kn = (kc + 16 < PH) ? kc + 16 : kc;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int j = kn + 4 * lg + t;
+          n0n[ct][t] = nc[ct][size_t(j) * rs];
+          n1n[ct][t] = nc[ct][size_t(PZ - 1 - j) * rs];
         }
 #pragma unroll
       for (int p = 0; p < 2; ++p)
@@ -2023,7 +2062,8 @@ hipError_t run_stage_t(const GridPlan& g, Work& w, const StageArgs& a, double* X
   const GridDev& d = g.dev;
   const int ntile = (d.Mx + MT - 1) / MT;
   constexpr bool pre = MT <= 2 && NZ <= 64;   // as in the kernel
-  const size_t lds = stage_lds<NZ, MT>(sizeof(Real), d.facT_stride, d.facP_stride, pre, SPLIT).total;
+  constexpr bool lean = SPLIT && NZ / 2 - 1 >= 64;
+  const size_t lds = stage_lds<NZ, MT>(sizeof(Real), d.facT_stride, d.facP_stride, pre, SPLIT, lean).total;
   hipLaunchKernelGGL((stage_kernel<Real, NZ, MT, SPLIT>), dim3(xcd_grid(d.one_xcd, n_slices * ntile)), dim3(kBlock),
                      lds, st, d, a, (const Real*)w.Nh, (const Real*)w.qbar, X, (Real*)w.Ehist, w.LYhist, (Real*)w.Q,
                      Eout, w.Yf);
