@@ -2,29 +2,38 @@
 """Benchmark of the Parareal hot path for 2D Rayleigh-Benard convection on
 one MI355X.
 
-Workload: Ra = 1e6, Pr = 1, aspect ratio 2, fine grid 256 x 64, 32 time
-slices over t in [0, 50], fine step 2e-4 (7813 steps per slice), coarse grid
-128 x 32 at step 2e-3, ARS(4,4,3), mixed precision (FP32 transforms and
-products, FP64 state, solves, correction, defect and Nusselt numbers).
+Headline (one bench "step" = one batched fine step of the whole fine
+propagator F over every time slice): Ra = 1e8, Pr = 1, aspect ratio 2, fine
+grid 1024 x 256, 64 slices of [0, 20] (fine step 2e-5), ARS(4,4,3), mixed
+precision (FP32 transforms and products on FP32 MFMA / vector units, FP64
+state, banded solves and Nusselt numbers).  The slice states are the coarse
+prediction (256 x 64 grid) of the seeded initial state, so every slice
+starts from its own state of the trajectory; Nusselt records are sampled
+every 50 fine steps inside the timed region.  `value` is fine DOF-steps per
+second: 64 slices x 1024 x 256 points x `--steps` batched steps over the
+wall time (inputs resident in HBM; events and a device synchronise on both
+sides).
 
-One timed step is one Parareal iteration.  The timed region is one whole
-Parareal run from the seeded initial state: the coarse prediction, then
-`--steps` iterations in the pipelined schedule (each slice's fine run starts
-as soon as its initial state is corrected and advances in one batch with
-every other run in flight; the serial coarse sweep overlaps them), with the
-correction U_{n+1} = G(U_n^new) + F(U_n^old) - G(U_n^old), the defect and
-Nusselt samples every 50 fine steps.  Iteration k runs F on slices k-1..S-1.
-`value` is the fine DOF-steps computed (grid points x fine steps x fine
-runs) per second of that wall time, so the coarse sweeps count against it.
-The same run in the sweep-then-batch order (bit-identical results) and the
-fine propagator alone at full batch are reported beside it.
+The roofline object is the per-mode stage of the step (forward transform,
+stage right-hand side and banded solves, inverse transform: the
+fwd_gemm, stage and inv_gemm kernels of one stage), timed with HIP events
+on the stream they run on around every stage of the timed steps, against
+the 3-pass minimum of 176 bytes per grid point and stage (mixed, ARS443):
+the 6 padded-grid fields it writes and the 2 it reads (12 x 4 bytes) and a
+quarter of the 64 FP64 stage-data values per grid point and step (state,
+right-hand-side history, stage writes).  The whole step's 896 bytes per
+DOF-step is reported beside it, with the x-pass.
 
-The roofline object describes the dominant kernel (the per-mode stage
-kernel): algorithmic bytes per launch from the byte model below (per state
-times the mean number of states in the timed launches), divided by its
-mean launch duration measured with HIP events on the stream it runs on
-during the timed run.  The cpu_baseline object times the FP64
-CPU oracle on one host core over a bounded number of fine steps of one slice.
+Legs beside the headline (skippable):
+  parareal_c2       one pipelined Parareal run at Ra 1e6, 256 x 64, 32
+                    slices (coarse prediction + 3 iterations) and the same
+                    run in the sweep-then-batch order (bit-identical);
+  time_to_solution  Parareal at that workload (FP64 switch on) to a defect
+                    of 1e-8 against the serial FP64 GPU stepper over the
+                    same window and fine step;
+  cpu_baseline      the FP64 CPU oracle on one host core: fine steps of one
+                    1024 x 256 slice (the headline's unit), and one
+                    64 x 32 slice.
 """
 from __future__ import annotations
 
@@ -32,6 +41,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -45,40 +55,43 @@ import rbc_inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 NU_STRIDE = 50
-TIMING_EVERY = 97
 
 
-def stage_kernel_bytes_per_dof_step(s: int, rb: int) -> float:
-    """Compulsory HBM bytes of the stage kernel per grid point and slice over
-    one fine step (all s stage launches).  Per launch i = 1..s it reads the
-    two product fields on the padded grid (2 x 1.5 values per point of Real),
-    the old state (2 doubles per point), the i-1 stored explicit terms (Real)
-    and i-1 stored implicit terms (FP64), and writes the explicit term and
-    the implicit term for later stages (i < s), the new state (i = s) and the
-    six padded-grid fields of the next x-pass (6 x 1.5 Real per point)."""
-    tot = 0.0
-    for i in range(1, s + 1):
-        tot += 2 * 1.5 * rb + 2 * 8 + (i - 1) * 2 * rb + (i - 1) * 2 * 8
-        if i < s:
-            tot += 2 * rb + 2 * 8
-        else:
-            tot += 2 * 8
-        tot += 6 * 1.5 * rb
-    return tot
+def stage_data_values(s: int) -> int:
+    """FP64 stage data per grid point and fine step (3-pass model): the old
+    state read by each of the s stages (2 fields), the right-hand-side
+    history of stage i (2 + 4 (i - 1) fields), and the writes of Y_i, E_i
+    and L Y_i (2 fields each) per stage."""
+    return 2 * s + sum(2 + 4 * (i - 1) for i in range(1, s + 1)) + 6 * s
 
 
-def xpass_bytes_per_dof_step(s: int, rb: int) -> float:
-    """x-pass: reads six padded-grid fields and writes two (per stage)."""
-    return s * (6 * 1.5 * rb + 2 * 1.5 * rb)
+def bytes_per_dof_step(s: int, b_bulk: int, b_state: int = 8) -> float:
+    """3-pass minimum HBM bytes per grid point and fine step: per stage the
+    inverse transform writes 6 padded-grid fields (1.5 values per point
+    each), the x-pass reads them and writes 2, the forward transform reads
+    those 2 (24 x 1.5 ... = 24 bulk values per point), plus the stage data."""
+    return 24 * s * b_bulk + stage_data_values(s) * b_state
+
+
+def stage_bytes_per_dof_launch(s: int, b_bulk: int, b_state: int = 8) -> float:
+    """The per-mode stage's share per stage: 8 of the 16 padded-grid field
+    passes (6 written, 2 read, 1.5 values per point each) and 1/s of the
+    stage data."""
+    return 12 * b_bulk + stage_data_values(s) * b_state / s
+
+
+def xpass_bytes_per_dof_launch(b_bulk: int) -> float:
+    """The x-pass per stage: reads 6 padded-grid fields, writes 2."""
+    return 12 * b_bulk
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per state of a stage-kernel launch from the committed PMC
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy, over the states
-    of the profiled launches), or None when the summary is for another
-    workload or the kernel source has changed since."""
+    """HBM bytes per state of one stage (the per-mode kernels of that stage)
+    from the committed PMC summary (FETCH_SIZE + WRITE_SIZE scaled by a
+    plain copy), or None when the summary is for another workload or the
+    kernel source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"stage_traffic_{workload}.txt")
     src = os.path.join(ROOT, "paper_2001_01609_amd", "csrc", "rbc_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -92,11 +105,23 @@ def measured_traffic(workload: str):
         cur = hashlib.sha256(f.read()).hexdigest()[:16]
     if kv.get("workload") != workload or kv.get("kernel_source_sha256_16") != cur:
         return None
-    return float(kv["bytes_per_launch"]) / float(kv["states_per_launch"])
+    return float(kv["bytes_per_stage"]) / float(kv["states_per_launch"])
 
 
-def cpu_baseline(w, seconds: float):
-    """Time the FP64 oracle's fine steps on one slice, one host thread."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_oracle_rate(w, seconds: float):
+    """The FP64 oracle's fine steps on one slice of workload w, one host
+    thread, for about `seconds` (setup not timed)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import rbc_oracle as O
@@ -108,13 +133,25 @@ def cpu_baseline(w, seconds: float):
         X = st.step(X)
         steps = 0
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
+        while time.perf_counter() - t0 < seconds or steps == 0:
             X = st.step(X)
             steps += 1
         el = time.perf_counter() - t0
-    return {"value": w.Nx * w.Nz * steps / el, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 fine steps of one {w.Nx}x{w.Nz} slice (ARS443, dt {dt:.6g}) "
-                      f"from the seeded initial state; {el:.1f} s on one thread"}
+    return w.Nx * w.Nz * steps / el, steps, el, dt
+
+
+def cpu_baseline(seconds: float):
+    """The oracle timed on the host: the headline's unit (one 1024 x 256
+    slice, ARS443) and the small plain case (one 64 x 32 slice, ARS222)."""
+    v3, n3, e3, dt3 = cpu_oracle_rate(I.C3, seconds)
+    v1, n1, e1, dt1 = cpu_oracle_rate(I.C1, max(seconds / 3, 2.0))
+    return {"value": v3, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "sample": f"{n3} FP64 fine steps of one 1024x256 slice (Ra 1e8, ARS443, dt {dt3:.3g}) from the "
+                      f"seeded initial state, {e3:.1f} s on one thread (operator setup not timed)",
+            "small_case": {"value": v1, "unit": "DOF-steps/s",
+                           "sample": f"{n1} FP64 fine steps of one 64x32 slice (Ra 1e4, ARS222, dt {dt1:.3g}), "
+                                     f"{e1:.1f} s on one thread"}}
 
 
 def q_visc(w) -> float:
@@ -132,6 +169,10 @@ def diag_time_averages(rec: np.ndarray, visc: float) -> np.ndarray:
     return np.array([nv, nb, nt, nu_int, ke, re, eps, P, abs(P - eps) / P])
 
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def time_to_solution(w, tol: float = 1e-8):
     """Parareal (this workload's precision with the FP64 switch, pipelined
     schedule) to a defect <= tol, against the serial FP64 fine stepper on one
@@ -144,7 +185,6 @@ def time_to_solution(w, tol: float = 1e-8):
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream(dev).cuda_stream
     S = w.n_slices
-    # Parareal
     p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0)
     h = R.rbc_create(p, st)
     try:
@@ -152,7 +192,7 @@ def time_to_solution(w, tol: float = 1e-8):
         U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
         R.rbc_init_state(h, w.seed, w.noise_amp, U)
         torch.cuda.synchronize()
-        print("[bench] time to solution: Parareal", file=sys.stderr, flush=True)
+        log("time to solution: Parareal")
         t0 = time.perf_counter()
         status, kd, defects, nu = R.parareal_iterate(h, U, S, tol, want_nu=True)
         torch.cuda.synchronize()
@@ -162,7 +202,6 @@ def time_to_solution(w, tol: float = 1e-8):
         u_end = U[S * n:].clone()
     finally:
         R.rbc_destroy(h)
-    # serial FP64 stepper: one run over the whole horizon
     q = R.params_from_workload(w, n_slices=1, precision=R.RBC_FP64, nu_stride=NU_STRIDE, nu_t_start=w.t0)
     q.dt_f = (w.t_end - w.t0) / S / math.ceil((w.t_end - w.t0) / S / w.dt_f - 1e-9)   # the Parareal fine step
     q.dt_c = q.dt_f
@@ -173,7 +212,7 @@ def time_to_solution(w, tol: float = 1e-8):
         R.rbc_init_state(h, w.seed, w.noise_amp, V)
         nus = torch.zeros((ns // NU_STRIDE) * R.RBC_DIAG, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
-        print(f"[bench] time to solution: serial FP64 ({ns} steps)", file=sys.stderr, flush=True)
+        log(f"time to solution: serial FP64 ({ns} steps)")
         t0 = time.perf_counter()
         R.rbc_fine_step_batch(h, V, V, 1, ns, nus)
         torch.cuda.synchronize()
@@ -184,7 +223,7 @@ def time_to_solution(w, tol: float = 1e-8):
         R.rbc_destroy(h)
     nu_par = nu[-1]
     fields = R.DIAG_AVG_FIELDS
-    return {"parareal_s": t_para, "serial_fp64_s": t_ser, "speedup": t_ser / t_para,
+    return {"workload": w.name, "parareal_s": t_para, "serial_fp64_s": t_ser, "speedup": t_ser / t_para,
             "iterations": kd, "fp64_from_iteration": k64, "iteration_done_at_s": report_at,
             "status": status, "tol": tol, "defects": [float(d) for d in defects],
             "serial_steps": ns,
@@ -194,23 +233,61 @@ def time_to_solution(w, tol: float = 1e-8):
             "final_state_rel_l2_vs_serial_fp64": rel}
 
 
+def parareal_leg(w, K: int):
+    """One pipelined Parareal run (coarse prediction + K iterations, Nusselt
+    samples every NU_STRIDE fine steps, no FP64 switch) and the same run in
+    the sweep-then-batch order."""
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev).cuda_stream
+    S = w.n_slices
+    out = {"workload": w.name, "iterations": K}
+    finals = []
+    for pipelined in (1, 0):
+        p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0, pipelined=pipelined)
+        h = R.rbc_create(p, st)
+        try:
+            n = R.rbc_state_size(h, 0)
+            nf, _ = R.rbc_steps_per_slice(h, 0)
+            U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
+            R.rbc_init_state(h, w.seed, w.noise_amp, U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, kd, defects, nu = R.parareal_iterate(h, U, K, 0.0, want_nu=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            finals.append(U.cpu().numpy())
+            runs = sum(S - k + 1 for k in range(1, kd + 1))
+            key = "pipelined" if pipelined else "sweep_then_batch"
+            out[key] = {"s": el, "fine_dof_steps_per_s": w.Nx * w.Nz * nf * runs / el, "defects": defects.tolist()}
+            if pipelined:
+                stats = R.rbc_get_pipeline_stats(h)
+                out[key]["scheduler"] = {k: v for k, v in stats.items() if k != "report_at_s"}
+                out[key]["averages_last"] = {f: float(v) for f, v in zip(R.DIAG_AVG_FIELDS, nu[-1])}
+            log(f"parareal leg ({key}): {K} iterations in {el:.2f} s")
+        finally:
+            R.rbc_destroy(h)
+    out["pipelined_speedup"] = out["sweep_then_batch"]["s"] / out["pipelined"]["s"]
+    out["bitwise_equal_to_sweep_then_batch"] = bool(np.array_equal(finals[0], finals[1]))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=I.C2.name, choices=sorted(I.WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample length (0 = skip)")
-    ap.add_argument("--no-tts", action="store_true",
-                    help="skip the Parareal vs serial FP64 time-to-solution comparison")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the sweep-then-batch run and the full-batch fine propagator (profiling: the "
-                         "fine kernels then run only in the timed pipelined run)")
+    ap.add_argument("--steps", type=int, default=200, help="timed batched fine steps")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed batched fine steps first")
+    ap.add_argument("--workload", default=I.C3.name, choices=sorted(I.WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample length (0 = skip)")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution leg")
+    ap.add_argument("--no-parareal", action="store_true", help="skip the Parareal throughput leg")
     ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
-                    help="counter-collection mode: only N batched fine steps (same kernels and launch "
-                         "shapes as the timed run), no Parareal iteration, no JSON line")
+                    help="counter-collection mode: only N batched fine steps of the headline (same kernels "
+                         "and launch shapes), no JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="also run one plain device-to-device copy of MIB MiB (reference for HBM byte counters)")
+                    help="also run one plain elementwise copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the slices of a run would shard "
@@ -225,127 +302,77 @@ def main() -> int:
     w = I.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    S = w.n_slices
-    K = args.steps
-    # the measured configuration: mixed precision throughout (no FP64 switch),
-    # Nu samples every NU_STRIDE fine steps, pipelined schedule
-    p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0, pipelined=1)
+    S, K, W = w.n_slices, args.steps, args.warmup
+    p = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0)
     h = R.rbc_create(p, stream.cuda_stream)
     try:
         n = R.rbc_state_size(h, 0)
         nf, dtf = R.rbc_steps_per_slice(h, 0)
-        ncs, dtc = R.rbc_steps_per_slice(h, 1)
         U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
-
-        def calibrate():
-            # reference kernels of known traffic for the HBM byte counters:
-            # a fill (writes N bytes), an elementwise scale by 1 into another
-            # buffer (reads N, writes N) and the runtime's device copy
+        R.rbc_init_state(h, w.seed, w.noise_amp, U)
+        if args.profile_steps > 0:
+            # counter runs serialise every dispatch: the seeded state in every
+            # slice instead of the coarse prediction (the work is the same)
+            U.view(S + 1, n)[1:] = U.view(S + 1, n)[0]
+        else:
+            log(f"{w.name}: coarse prediction for the slice states")
+            R.parareal_iterate(h, U, 0, 0.0)
+        F = U[: S * n].clone()
+        del U
+        torch.cuda.synchronize()
+        if args.profile_steps > 0:
+            R.rbc_fine_step_batch(h, F, F, S, args.profile_steps, None)
+            torch.cuda.synchronize()
             if args.calibrate_copy > 0:
                 a = torch.empty(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
                 b = torch.empty_like(a)
                 a.fill_(1.0)
                 torch.mul(a, 1.0, out=b)
-                b.copy_(a)
                 torch.cuda.synchronize()
                 del a, b
-
-        if args.profile_steps > 0:
-            # the fine propagator's kernels at full batch from the seeded state
-            F = torch.zeros(S * n, dtype=torch.float64, device=dev)
-            R.rbc_init_state(h, w.seed, w.noise_amp, F)
-            F.view(S, n)[1:] = F.view(S, n)[0]
-            R.rbc_fine_step_batch(h, F, F, S, args.profile_steps, None)
-            torch.cuda.synchronize()
-            calibrate()
-            print(f"[bench] profile mode: {args.profile_steps} batched fine steps done", file=sys.stderr)
+            log(f"profile mode: {args.profile_steps} batched fine steps done")
             return 0
-
-        def parareal(k):
-            U.zero_()
-            R.rbc_init_state(h, w.seed, w.noise_amp, U)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, kd, defects, nu = R.parareal_iterate(h, U, k, 0.0, want_nu=True)
-            torch.cuda.synchronize()
-            return time.perf_counter() - t0, kd, defects, nu
-
-        for it in range(args.warmup):
-            parareal(1)
-            print(f"[bench] warmup Parareal run {it + 1}/{args.warmup} (1 iteration) done", file=sys.stderr,
-                  flush=True)
-        R.rbc_kernel_timing_enable(h, 0, TIMING_EVERY)
-        el, kd, defects, nu_hist = parareal(K)
+        # warmup, the x-pass timed with events in its first half
+        R.rbc_kernel_timing_enable(h, 1, 1)
+        R.rbc_fine_step_batch(h, F, F, S, max(W // 2, 1), None)
+        x_ms, x_cnt, x_batch = R.rbc_kernel_timing(h)
+        R.rbc_kernel_timing_enable(h, -1, 0)
+        R.rbc_fine_step_batch(h, F, F, S, max(W - W // 2, 1), None)
+        nus = torch.zeros(S * (K // NU_STRIDE) * R.RBC_DIAG, dtype=torch.float64, device=dev)
+        R.rbc_kernel_timing_enable(h, 0, 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        R.rbc_fine_step_batch(h, F, F, S, K, nus)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ev_ms = e0.elapsed_time(e1)
         k_ms, k_cnt, k_batch = R.rbc_kernel_timing(h)
         R.rbc_kernel_timing_enable(h, -1, 0)
-        pstats = R.rbc_get_pipeline_stats(h)
-        print(f"[bench] timed pipelined Parareal: {K} iterations in {el:.2f} s", file=sys.stderr, flush=True)
-        u_pipe = U.cpu().numpy()
-        finite = bool(np.isfinite(u_pipe).all())
-        # fine propagator alone at full batch (events around one batched F
-        # call; the stage kernel timed inside it as well)
-        full = None
-        if not args.no_compare:
-            F = U[:S * n].clone()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            R.rbc_kernel_timing_enable(h, 0, TIMING_EVERY)
-            e0.record(stream)
-            R.rbc_fine_step_batch(h, F, F, S, nf, None)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            f_ms = e0.elapsed_time(e1)
-            kf_ms, kf_cnt, kf_batch = R.rbc_kernel_timing(h)
-            R.rbc_kernel_timing_enable(h, -1, 0)
-            full = (f_ms, kf_ms, kf_cnt, kf_batch)
-            calibrate()
+        finite = bool(torch.isfinite(F).all().item()) and bool(torch.isfinite(nus).all().item())
+        rec = nus.view(S, -1, R.RBC_DIAG).cpu().numpy()
+        log(f"headline: {K} batched steps of {S} slices in {el:.3f} s")
     finally:
-        # one handle at a time: each holds two streams, and a process has few
-        # hardware queues (two live handles can leave the fine and coarse
-        # streams of the next one on a shared queue, without overlap)
         R.rbc_destroy(h)
-    # the same K iterations in the sweep-then-batch order (same results, bit for bit)
-    seq = None
-    if not args.no_compare:
-        q = R.params_from_workload(w, nu_stride=NU_STRIDE, nu_t_start=w.t0, promote_fp64=0, pipelined=0)
-        h = R.rbc_create(q, stream.cuda_stream)
-        try:
-            U.zero_()
-            R.rbc_init_state(h, w.seed, w.noise_amp, U)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            R.parareal_iterate(h, U, K, 0.0, want_nu=True)
-            torch.cuda.synchronize()
-            el_seq = time.perf_counter() - t0
-            seq = (el_seq, bool(np.array_equal(U.cpu().numpy(), u_pipe)))
-            print(f"[bench] sweep-then-batch Parareal: {K} iterations in {el_seq:.2f} s", file=sys.stderr,
-                  flush=True)
-        finally:
-            R.rbc_destroy(h)
-    return emit(args, w, K, el, kd, defects, nu_hist, finite, k_ms, k_cnt, k_batch, pstats, nf, ncs, seq, full)
-
-
-def emit(args, w, K, el, kd, defects, nu_hist, finite, k_ms, k_cnt, k_batch, pstats, nf, ncs, seq, full):
-    """Prints the JSON line (the timed run's figures and the optional legs)."""
-    from paper_2001_01609_amd import rbc as R
-    S = w.n_slices
 
     dof = w.Nx * w.Nz
-    runs = sum(S - k + 1 for k in range(1, K + 1))      # fine runs of iterations 1..K
-    fine_dof_steps = dof * nf * runs
-    value = fine_dof_steps / el
-    rb = 4 if w.mixed else 8
+    value = S * dof * K / el
+    b_bulk = 4 if w.mixed else 8
     s = w.scheme
-    per_state = stage_kernel_bytes_per_dof_step(s, rb) / s * dof
-    per_launch = per_state * k_batch
-    achieved = per_launch / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    stage_b = stage_bytes_per_dof_launch(s, b_bulk) * dof * k_batch
+    achieved = stage_b / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    step_b = bytes_per_dof_step(s, b_bulk)
     traffic_state = measured_traffic(w.name)
+    x_b = xpass_bytes_per_dof_launch(b_bulk) * dof * x_batch
     out = {
         "metric": "fine-step DOF-steps/s (%HBM roofline); Parareal vs serial time-to-solution",
         "value": value,
         "unit": "DOF-steps/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
+        "warmup": W,
         "ms_per_step": 1e3 * el / K,
         "higher_is_better": True,
         "scaling": "weak",
@@ -353,43 +380,34 @@ def emit(args, w, K, el, kd, defects, nu_hist, finite, k_ms, k_cnt, k_batch, pst
         "dtype": "f32+f64" if w.mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "Ra": w.Ra, "Pr": w.Pr, "grid": [w.Nx, w.Nz],
-                   "coarse_grid": [w.Nx_c, w.Nz_c], "slices": S, "t": [w.t0, w.t_end],
-                   "fine_steps_per_slice": nf, "coarse_steps_per_slice": ncs,
-                   "scheme": "ARS443" if s == 4 else "ARS222",
-                   "step": "one Parareal iteration (pipelined schedule; the timed run is the coarse "
-                           "prediction and `steps` iterations from the seeded state, fine runs of "
-                           "iteration k on slices k-1..S-1)"},
-        "roofline": {"bound": "hbm", "kernel": "stage_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                   "coarse_grid": [w.Nx_c, w.Nz_c], "slices": S, "t": [w.t0, w.t_end], "dt_f": dtf,
+                   "fine_steps_per_slice": nf, "scheme": "ARS443" if s == 4 else "ARS222",
+                   "nu_stride": NU_STRIDE,
+                   "step": "one batched fine step of every slice (all stages: x-pass, forward transform, "
+                           "right-hand side, banded solves, inverse transform), Nusselt records every "
+                           f"{NU_STRIDE} steps; slice states from the coarse prediction of the seeded state"},
+        "roofline": {"bound": "hbm", "kernel": "per-mode stage (fwd_gemm + stage + inv_gemm kernels of one stage)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_state * k_batch if traffic_state else None,
-                     "bytes_per_launch": per_launch, "mean_launch_ms": k_ms, "timed_launches": k_cnt,
-                     "mean_slices_per_launch": k_batch},
-        "parareal": {"iterations": kd, "defects": [float(d) for d in defects], "fine_runs": runs,
-                     "averages_last": {f: float(v) for f, v in zip(R.DIAG_AVG_FIELDS, nu_hist[-1])},
-                     "finite": finite,
-                     "scheduler": {k: v for k, v in pstats.items() if k != "report_at_s"}},
+                     "bytes_per_launch": stage_b, "bytes_per_dof_launch": stage_bytes_per_dof_launch(s, b_bulk),
+                     "mean_launch_ms": k_ms, "timed_launches": k_cnt, "slices_per_launch": k_batch},
+        "step_roofline": {"bytes_per_dof_step": step_b, "achieved_gbs": step_b * S * dof * K / el / 1e9,
+                          "frac": step_b * S * dof * K / el / 1e9 / HBM_PEAK_GBS,
+                          "event_ms_per_step": ev_ms / K},
+        "xpass": {"mean_launch_ms": x_ms, "timed_launches": x_cnt,
+                  "achieved_gbs": x_b / (x_ms * 1e-3) / 1e9 if x_ms > 0 else 0.0,
+                  "frac": x_b / (x_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if x_ms > 0 else 0.0},
+        "finite": finite,
+        "nusselt_last_sample": {"Nu_V_first_slice": float(rec[0, -1, 0]), "Nu_V_last_slice": float(rec[-1, -1, 0])}
+        if rec.shape[1] else None,
     }
-    if seq is not None:
-        el_seq, same = seq
-        out["parareal"].update({"sweep_then_batch_s": el_seq, "sweep_then_batch_value": fine_dof_steps / el_seq,
-                                "pipelined_speedup": el_seq / el, "bitwise_equal_to_sweep_then_batch": same})
-    if full is not None:
-        f_ms, kf_ms, kf_cnt, kf_batch = full
-        achieved_full = per_state * kf_batch / (kf_ms * 1e-3) / 1e9 if kf_ms > 0 else 0.0
-        out["fine_propagator"] = {
-            "dof_steps_per_s": dof * S * nf / (f_ms * 1e-3), "ms_per_call": f_ms,
-            "us_per_batched_step": 1e3 * f_ms / nf, "slices": S,
-            "stage_kernel": {"mean_launch_ms": kf_ms, "timed_launches": kf_cnt,
-                             "bytes_per_launch": per_state * kf_batch, "achieved_gbs": achieved_full,
-                             "frac": achieved_full / HBM_PEAK_GBS,
-                             "traffic": traffic_state * kf_batch if traffic_state else None},
-            "bytes_per_dof_step_model": stage_kernel_bytes_per_dof_step(s, rb) + xpass_bytes_per_dof_step(s, rb)}
+    if not args.no_parareal:
+        out["parareal_c2"] = parareal_leg(I.C2, 3)
     if not args.no_tts:
-        out["time_to_solution"] = time_to_solution(w)
+        out["time_to_solution"] = time_to_solution(I.C2)
     if args.cpu_seconds > 0:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        cb = cpu_baseline(w, args.cpu_seconds)
-        out["cpu_baseline"] = cb
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -1565,6 +1565,18 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Block -> (map slab `part`, column sequence bi of nb) of a persistent GEMM
+// grid of parts x nb blocks (nb a multiple of kXcds).  The `parts` blocks
+// that walk one column sequence sit on one XCD (workgroup b runs on XCD
+// b mod kXcds), so each column operand they all read is fetched once into
+// that XCD's L2.
+__device__ __forceinline__ void gemm_block(int parts, int* part, int* bi, int* nb) {
+  const int x = blockIdx.x % kXcds, w = blockIdx.x / kXcds;
+  *part = w % parts;
+  *bi = (w / parts) * kXcds + x;
+  *nb = gridDim.x / parts;
+}
+
 __device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -1605,7 +1617,8 @@ inv_gemm_kernel(GridDev g, const float* __restrict__ Yf, float* __restrict__ Q, 
   constexpr int NH = S::NH, PH = S::PH, PZ = S::PZ, JT = S::JT, RT = S::RT, LDA = S::LDA, NJT = S::NJT;
   extern __shared__ __align__(16) unsigned char smem[];
   float* sA = reinterpret_cast<float*>(smem);   // [q][parity][JT][LDA]
-  const int jt = blockIdx.x % NJT, bi = blockIdx.x / NJT, nb = gridDim.x / NJT;
+  int jt, bi, nb;
+  gemm_block(NJT, &jt, &bi, &nb);
   const int j0 = jt * JT;
   const int tid = threadIdx.x;
   for (int e = tid; e < 4 * 2 * JT * (NH / 4); e += 256) {
@@ -1728,7 +1741,8 @@ fwd_gemm_kernel(GridDev g, const float* __restrict__ Nh, float* __restrict__ E, 
                 CT = S::CT, GM = S::GM;
   extern __shared__ __align__(16) unsigned char smem[];
   float* sA = reinterpret_cast<float*>(smem);   // [parity][RH][LDA]
-  const int fh = blockIdx.x % (2 * NRH), bi = blockIdx.x / (2 * NRH), nb = gridDim.x / (2 * NRH);
+  int fh, bi, nb;
+  gemm_block(2 * NRH, &fh, &bi, &nb);
   const int f = fh / NRH, h = fh - f * NRH;
   const int tid = threadIdx.x;
   for (int e = tid; e < 2 * RH * (PH / 4); e += 256) {
@@ -2093,14 +2107,16 @@ hipError_t run_stage_nz(const GridPlan& g, Work& w, const StageArgs& a, double* 
 }
 
 // Persistent grid of a GEMM kernel: `parts` map slabs, each with as many
-// blocks as fit on the device next to the others (by LDS), at most one per
-// column group.
+// blocks as fit on the device next to the others (by LDS), a multiple of
+// kXcds (see gemm_block), no more than the column groups need.
 inline int gemm_blocks(int parts, size_t lds, int ngroups) {
   int per_cu = int((160 * 1024) / (lds ? lds : 1));
   per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
   int nb = (256 * per_cu) / parts;
-  if (nb > ngroups) nb = ngroups;
-  if (nb < 1) nb = 1;
+  const int need = (ngroups + kXcds - 1) / kXcds * kXcds;
+  if (nb > need) nb = need;
+  nb = nb / kXcds * kXcds;
+  if (nb < kXcds) nb = kXcds;
   return parts * nb;
 }
 

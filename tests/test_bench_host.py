@@ -13,14 +13,18 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_stage_kernel_byte_model():
-    # mixed precision (4-byte bulk data), ARS443 (four stages): the per-DOF
-    # traffic of one fine step, term by term
-    reads = 4 * 12 + 4 * 16 + (0 + 1 + 2 + 3) * 8 + (0 + 1 + 2 + 3) * 16
-    writes = 3 * (8 + 16) + 16 + 4 * 36
-    assert bench.stage_kernel_bytes_per_dof_step(4, 4) == reads + writes == 488
-    # FP64 doubles the bulk terms only
-    assert bench.stage_kernel_bytes_per_dof_step(4, 8) == 488 + 4 * 12 + 6 * 8 + 3 * 8 + 4 * 36
+def test_byte_model_of_the_three_pass_step():
+    # stage data per grid point and step: s state reads, the right-hand-side
+    # history 2 + 4 (i - 1) of stage i, 6 writes per stage
+    assert bench.stage_data_values(4) == 8 + (2 + 6 + 10 + 14) + 24 == 64
+    assert bench.stage_data_values(2) == 4 + (2 + 6) + 12 == 24
+    # ARS443: 896 B mixed, 1280 B FP64; ARS222: 384 B and 576 B
+    assert bench.bytes_per_dof_step(4, 4) == 96 * 4 + 64 * 8 == 896
+    assert bench.bytes_per_dof_step(4, 8) == 1280
+    assert bench.bytes_per_dof_step(2, 4) == 384 and bench.bytes_per_dof_step(2, 8) == 576
+    # per stage: the per-mode stage's 176 B and the x-pass's 48 B make up the step
+    st, xp = bench.stage_bytes_per_dof_launch(4, 4), bench.xpass_bytes_per_dof_launch(4)
+    assert st == 176 and xp == 48 and 4 * (st + xp) == 896
 
 
 def test_more_than_one_gpu_is_refused():
