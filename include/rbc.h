@@ -286,6 +286,49 @@ rbc_status rbc_nusselt(rbc_handle h, const double* U_dev, int32_t n_states, doub
  * fine states into out_host[n_states][RBC_DIAG].  Synchronises. */
 rbc_status rbc_diagnostics(rbc_handle h, const double* U_dev, int32_t n_states, double* out_host);
 
+/* Ensembles of independent Parareal runs on one device (many runs of
+ * different Rayleigh number, grid, step and horizon; section 3.1, Eq. 19 per
+ * run).  Each run is the iteration of parareal_iterate in the
+ * sweep-then-batch order (pipelined = 0, no FP64 switch: promote_fp64 is
+ * ignored): its iterates, defects and stop are those of a handle created
+ * with the same parameters, bit for bit.  One rbc_ensemble_step advances
+ * every active run by one iteration (a new run: its coarse prediction):
+ * the fine runs of all runs of one fine grid shape advance in one batch per
+ * stage launch, ordered by their fine steps per slice (a cost-ordered work
+ * list), and the serial coarse sweeps of all runs go in lock step, the
+ * coarse steps of all runs of one coarse grid shape batched.  Runs may be
+ * added between steps; they join at the next step (continuous batching).
+ * Run buffers (iterates, fine results, coarse parts, tables) belong to the
+ * ensemble from rbc_ensemble_add until rbc_ensemble_release.  Calls are
+ * enqueued on the stream given at create; rbc_ensemble_step synchronises
+ * (it reads the defects).  An ensemble is not thread-safe. */
+typedef struct rbc_ensemble_s* rbc_ensemble;
+rbc_status rbc_ensemble_create(void* hip_stream, rbc_ensemble* out);
+rbc_status rbc_ensemble_destroy(rbc_ensemble e);
+const char* rbc_ensemble_last_error(rbc_ensemble e);
+/* Device bytes one run of these parameters needs in an ensemble (its
+ * tables, buffers and its share of the batch work arrays): for admission
+ * against the free device memory. */
+rbc_status rbc_ensemble_footprint(const rbc_params* p, size_t* bytes);
+/* Adds a run from the fine initial state U0_dev (copied; caller-owned),
+ * stopping at defect <= tol, at k_max iterations or at k = n_slices;
+ * *run_id identifies it (ids are not reused). */
+rbc_status rbc_ensemble_add(rbc_ensemble e, const rbc_params* p, const double* U0_dev, int32_t k_max, double tol,
+                            int32_t* run_id);
+/* One iteration of every active run; *n_active = runs still active after it. */
+rbc_status rbc_ensemble_step(rbc_ensemble e, int32_t* n_active);
+/* Run state (0 active, 1 done, 2 failed on a non-finite value, 3 released),
+ * iterations done, the rbc_stop of a finished run (-1 otherwise) and the
+ * first hist_len defects (defect_hist may be NULL). */
+rbc_status rbc_ensemble_run_info(rbc_ensemble e, int32_t run_id, int32_t* state, int32_t* k_done, int32_t* stop,
+                                 double* defect_hist, int32_t hist_len);
+/* Copies the run's iterate U^k ([n_slices+1][state]) to U_dev. */
+rbc_status rbc_ensemble_result(rbc_ensemble e, int32_t run_id, double* U_dev);
+/* Frees a finished run's buffers. */
+rbc_status rbc_ensemble_release(rbc_ensemble e, int32_t run_id);
+/* Device bytes the run holds. */
+rbc_status rbc_ensemble_run_bytes(rbc_ensemble e, int32_t run_id, size_t* bytes);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * records of rbc_diagnostics written to caller-owned device memory

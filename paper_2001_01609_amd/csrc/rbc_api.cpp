@@ -165,6 +165,49 @@ void sampling(const rbc_params* p, int nf, int nc, double dtf, double dtc, int* 
 
 }  // namespace
 
+namespace rbc {
+
+// The fine and coarse plans of one run, built and uploaded as rbc_create
+// builds them (without the FP64 promotion plans); returns "" or the error.
+std::string make_run_plans(const rbc_params* p, GridPlan& fine, GridPlan& coarse, int* nf, int* nc) {
+  std::string e = check_params(p);
+  if (!e.empty()) return e;
+  double dtf, dtc;
+  *nf = steps_for(p->t0, p->t_end, p->n_slices, p->dt_f, &dtf);
+  *nc = steps_for(p->t0, p->t_end, p->n_slices, p->dt_c, &dtc);
+  setup_grid(fine, p, false, dtf);
+  setup_grid(coarse, p, true, dtc);
+  e = build_plan(fine);
+  if (e.empty()) e = build_plan(coarse);
+  if (!e.empty()) return e;
+  hipError_t he;
+  if ((he = upload_plan(fine)) != hipSuccess || (he = upload_plan(coarse)) != hipSuccess)
+    return std::string("table upload: ") + hipGetErrorString(he);
+  return "";
+}
+
+size_t run_plan_bytes(const rbc_params* p, int* nf, int* nc, GridPlan* fine_shape, GridPlan* coarse_shape) {
+  double dtf, dtc;
+  *nf = steps_for(p->t0, p->t_end, p->n_slices, p->dt_f, &dtf);
+  *nc = steps_for(p->t0, p->t_end, p->n_slices, p->dt_c, &dtc);
+  setup_grid(*fine_shape, p, false, dtf);
+  setup_grid(*coarse_shape, p, true, dtc);
+  fine_shape->tab = make_tableau(fine_shape->scheme);
+  coarse_shape->tab = make_tableau(coarse_shape->scheme);
+  auto tables = [](const GridPlan& g) {
+    size_t n = g.Nz / 2, rb = g.mixed ? 4 : 8;
+    size_t d = 2 * n * 14 + size_t(g.Mx) * 2 * (kFacT * n + 4) + size_t(g.Mx) * 2 * (kFacP * n + 4);
+    size_t r = size_t(4) * (g.Pz / 2) * g.Nz + size_t(3) * g.Nz * (g.Pz / 2) + 2 * size_t(g.Px);
+    if (g.split) r += size_t(4) * (g.Pz / 2) * g.Nz + size_t(2) * g.Nz * (g.Pz / 2);
+    return d * 8 + r * rb + 16 * 256 + sizeof(RunDev);
+  };
+  return tables(*fine_shape) + tables(*coarse_shape);
+}
+
+std::string params_error(const rbc_params* p) { return check_params(p); }
+
+}  // namespace rbc
+
 extern "C" {
 
 rbc_status rbc_default_params(rbc_params* p) {

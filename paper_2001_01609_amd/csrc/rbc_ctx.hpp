@@ -61,6 +61,13 @@ namespace rbc {
 
 constexpr int kCoarseGraphSteps = 8;
 
+// Plans of one run as rbc_create builds them (rbc_api.cpp): "" or the error.
+std::string make_run_plans(const rbc_params* p, GridPlan& fine, GridPlan& coarse, int* nf, int* nc);
+// Device bytes of those plans' tables; fills the grid shapes and step counts.
+size_t run_plan_bytes(const rbc_params* p, int* nf, int* nc, GridPlan* fine_shape, GridPlan* coarse_shape);
+// Parameter validation of rbc_create: "" or the error.
+std::string params_error(const rbc_params* p);
+
 rbc_status fail(rbc_handle h, rbc_status s, const std::string& msg);
 
 }  // namespace rbc

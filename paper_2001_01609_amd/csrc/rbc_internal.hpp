@@ -47,6 +47,18 @@ struct Tableau {
 };
 Tableau make_tableau(int scheme);
 
+// Parameters of one run of an ensemble launch (runs of one grid that
+// differ in Rayleigh number and step): band factors, diffusivities, and the
+// stage coefficients dt a_ij of the tableau, [stage i][j], as the host forms
+// them for a single run.
+struct RunDev {
+  const double* facT;
+  const double* facP;
+  double nu, kappa, sqrtRaPr;
+  double hae[kMaxStages][kMaxStages];
+  double hai[kMaxStages][kMaxStages];
+};
+
 // Device view of one grid, passed to kernels by value.
 struct GridDev {
   int Nx, Nz, Mx, Px, Pz, n;      // n = Nz / 2
@@ -76,6 +88,13 @@ struct GridDev {
   const void* Winv;               // Real [4][Pz/2][Nz]: d^q T_n / dz^q at Gauss points
   const void* Wfwd;               // Real [3][Nz][Pz/2]: folded forward maps (psi, T, u_bar rows)
   const void* tw;                 // Real2 [Px]: exp(-2 pi i t / Px)
+  // Gather launches of an ensemble (null otherwise): batch position b works
+  // on the state at xptrs[b] with the run parameters rptrs[b] (in place of
+  // the grid's own factors, diffusivities and stage coefficients); its work
+  // arrays are those of slot b.
+  const double* const* xptrs;
+  const RunDev* const* rptrs;
+  const RunDev* run0;             // this grid's own run parameters (device memory)
   const float* Winv2;             // split path: [4 q][2 p][Pz/2 j][Nz/2 i] = Winv[q][j][2 i + p]
   const float* Wfwd2;             // split path: [2 f][2 p][Nz/2 i][Pz/2 j] = Wfwd[f][2 i + p][j]
   int nrad, rad[12];              // FFT radix plan for Px
@@ -100,6 +119,7 @@ struct GridPlan {
   bool split = false;
   // host tables
   std::vector<double> bS10, bD2, bA, bB, bD4, facT, facP, Winv, Wfwd, tw, Winv2, Wfwd2;
+
   int facT_stride = 0, facP_stride = 0;
   double max_growth = 0;
   // device copies
@@ -109,6 +129,9 @@ struct GridPlan {
 
 // Builds every host table of a grid; returns an empty string or an error.
 std::string build_plan(GridPlan& g);
+// The run parameters of plan g with its band factors at the given device
+// addresses (the grid's own, or those of one run of an ensemble).
+RunDev make_run_dev(const GridPlan& g, const double* facT_dev, const double* facP_dev);
 // Uploads the tables and fills g.dev.  Returns hipSuccess or the error.
 hipError_t upload_plan(GridPlan& g);
 size_t plan_device_bytes(const GridPlan& g);

@@ -57,6 +57,28 @@ __device__ __forceinline__ int ring_slot(int b, int slot0, int cap) {
   const int s = slot0 + b;
   return s >= cap ? s - cap : s;
 }
+
+// A pointer that is the same for the whole wavefront, kept in scalar
+// registers.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v)), hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
+  return reinterpret_cast<T*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// State of batch position b: gathered from the ensemble's pointer table, or
+// slot s of the launch's state array X.
+__device__ __forceinline__ const double* batch_state(const GridDev& g, const double* X, int b, int s) {
+  return g.xptrs ? uniform_ptr(g.xptrs[b]) : X + size_t(s) * g.state;
+}
+
+// Run parameters of batch position b: the ensemble's table, or the grid's
+// own (always device memory, so that choosing between them never needs the
+// address of a kernel argument).
+__device__ __forceinline__ const RunDev* batch_run(const GridDev& g, int b) {
+  return g.rptrs ? uniform_ptr(g.rptrs[b]) : g.run0;
+}
 template <typename Real>
 __device__ __forceinline__ Cx<Real> csub(Cx<Real> a, Cx<Real> b) { return {a.x - b.x, a.y - b.y}; }
 
@@ -889,6 +911,16 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   const int s = ring_slot(b, a.slot0, a.cap);
   const int m0 = tile * MT;
   const int st = g.state;
+  // this slot's run (ensemble launches): factors, diffusivities, stage
+  // coefficients h a_ij of this stage
+  const RunDev* rd = batch_run(g, b);
+  const double* facTg = rd->facT;
+  const double* facPg = rd->facP;
+  const double nu_r = rd->nu, kappa_r = rd->kappa;
+  const int si = a.stage;
+  auto HAE = [rd, si](int j) { return rd->hae[si][j]; };
+  auto HAI = [rd, si](int j) { return rd->hai[si][j]; };
+  const double haii = rd->hai[si][si];
   double* sY = reinterpret_cast<double*>(smem);
   double* sX = sY + 4 * MT * LD;   // not used by the lean variant
   unsigned char* uni = reinterpret_cast<unsigned char*>(kLean ? sX : sX + 4 * MT * LD);
@@ -906,7 +938,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   auto goff = [&](int c) {
     return size_t((fld(c) * Mx + m0 + mtc(c)) * 2 + (c & 1)) * NZ;
   };
-  const double* Xs = X + size_t(s) * st;
+  const double* Xs = batch_state(g, X, b, s);
 
   // ---- kPre: entry loads into registers (stored to LDS by pre_store)
   constexpr int FTN = (MT * 2 * 2 * NZ + kBlock - 1) / kBlock;        // facT stride 2 Nz
@@ -918,8 +950,8 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   const int nmt = min(MT, Mx - m0);
   const int totT = stg ? nmt * 2 * g.facT_stride : 0, totP = stg ? nmt * 2 * g.facP_stride : 0;
   if constexpr (kPre) {
-    const double* srcT = g.facT + size_t(m0) * 2 * g.facT_stride;
-    const double* srcP = g.facP + size_t(m0) * 2 * g.facP_stride;
+    const double* srcT = facTg + size_t(m0) * 2 * g.facT_stride;
+    const double* srcP = facPg + size_t(m0) * 2 * g.facP_stride;
 #pragma unroll
     for (int u = 0; u < FTN; ++u) {
       const int e = tid + u * kBlock;
@@ -966,11 +998,11 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       // factor blocks longer than the register bound (not for the plans built here)
       for (int e = FTN * kBlock + tid; e < totT; e += kBlock) {
         const int bb = e / g.facT_stride;
-        sFT[bb * lsT + (e - bb * g.facT_stride)] = g.facT[size_t(m0) * 2 * g.facT_stride + e];
+        sFT[bb * lsT + (e - bb * g.facT_stride)] = facTg[size_t(m0) * 2 * g.facT_stride + e];
       }
       for (int e = FPN * kBlock + tid; e < totP; e += kBlock) {
         const int bb = e / g.facP_stride;
-        sFP[bb * lsP + (e - bb * g.facP_stride)] = g.facP[size_t(m0) * 2 * g.facP_stride + e];
+        sFP[bb * lsP + (e - bb * g.facP_stride)] = facPg[size_t(m0) * 2 * g.facP_stride + e];
       }
     }
   };
@@ -1028,7 +1060,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           Eout[o0] = E;
           Eout[o1] = 0.0;
         } else {
-          sY[0 * LD + rr] = a.hae[a.stage - 1] * E;
+          sY[0 * LD + rr] = HAE(a.stage - 1) * E;
           sY[1 * LD + rr] = 0.0;
           if (a.store_E) {
             Real* eh = Ehist + (size_t(a.stage - 1) * a.cap + s) * st;
@@ -1047,7 +1079,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (a.mode == kModeExplicit) {
           Eout[off] = E;
         } else {
-          sY[((f * MT + mt) * 2 + ri) * LD + rr] = a.hae[a.stage - 1] * E;
+          sY[((f * MT + mt) * 2 + ri) * LD + rr] = HAE(a.stage - 1) * E;
           if (a.store_E) Ehist[(size_t(a.stage - 1) * a.cap + s) * st + off] = Real(E);
         }
       }
@@ -1070,7 +1102,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (a.mode == kModeExplicit)
           Eout[goff(c) + r] = E;
         else
-          sY[yoff(c) + r] = a.hae[a.stage - 1] * E;
+          sY[yoff(c) + r] = HAE(a.stage - 1) * E;
       }
       if (m0 == 0)
         for (int rr = tid; rr < NZ - 2; rr += kBlock) {
@@ -1163,7 +1195,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     if (a.mode == kModeExplicit) return;
     __syncthreads();
     // temperature factors into the (now free) union region
-    if constexpr (!kPre && !kLean) stage_factors<MT>(sFT, g.facT, g.facT_stride, m0, Mx);
+    if constexpr (!kPre && !kLean) stage_factors<MT>(sFT, facTg, g.facT_stride, m0, Mx);
     // ---- phase C: right-hand side of stage i on this thread's row
     const RowTables tb = kPre ? tbp : load_row_tables(g, r);
     {
@@ -1197,15 +1229,15 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if constexpr (kPre) {
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj)
-            if (jj + 1 < a.stage) h += a.hae[jj] * hE[kc][jj];
+            if (jj + 1 < a.stage) h += HAE(jj) * hE[kc][jj];
 #pragma unroll
           for (int jj = 1; jj < 4; ++jj)
-            if (jj < a.stage) h += a.hai[jj] * hL[kc][jj - 1];
+            if (jj < a.stage) h += HAI(jj) * hL[kc][jj - 1];
         } else {
           for (int jj = 0; jj + 1 < a.stage; ++jj)
-            h += a.hae[jj] * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
+            h += HAE(jj) * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
           for (int jj = 1; jj < a.stage; ++jj)
-            h += a.hai[jj] * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
+            h += HAI(jj) * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
         }
         acc[kc] = h;
       }
@@ -1230,7 +1262,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           if (m < Mx) {
             double gbc = 0.0;
             if (m == 0 && ri == 0) gbc = g.bcT[p];
-            const double* fac = kLean ? g.facT + (size_t(m) * 2 + p) * g.facT_stride
+            const double* fac = kLean ? facTg + (size_t(m) * 2 + p) * g.facT_stride
                                       : sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride);
             solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(
                 sY + ((MT + mt) * 2 + ri) * LD, p, fac, gbc, g.fluxT != 0, li);
@@ -1262,7 +1294,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     }
     __syncthreads();
     // flow factors; implicit buoyancy of the new temperature into psi
-    if constexpr (!kPre && !kLean) stage_factors<MT>(sFP, g.facP, g.facP_stride, m0, Mx);
+    if constexpr (!kPre && !kLean) stage_factors<MT>(sFP, facPg, g.facP_stride, m0, Mx);
     if (r < NZ - 4) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
@@ -1276,7 +1308,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
 #pragma unroll
         for (int t = 0; t < 5; ++t)
           if (r + 2 * t < NZ) sb += tb.b[t] * tv[r + 2 * t];
-        sY[yoff(c) + r] += a.haii * (ri == 0 ? k * sb : -k * sb);
+        sY[yoff(c) + r] += haii * (ri == 0 ? k * sb : -k * sb);
       }
     }
     __syncthreads();
@@ -1286,7 +1318,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (sys < 4 * MT) {
           const int mt = sys >> 2, p = (sys >> 1) & 1, ri = sys & 1, m = m0 + mt;
           if (m < Mx) {
-            const double* fac = kLean ? g.facP + (size_t(m) * 2 + p) * g.facP_stride
+            const double* fac = kLean ? facPg + (size_t(m) * 2 + p) * g.facP_stride
                                       : sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
             double* v = sY + (mt * 2 + ri) * LD;
             if (m == 0)
@@ -1339,9 +1371,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         double L;
         if (f == 1) {
           const double sm = tb.s10[0] * yv[r] + tb.s10[1] * yv[r + 2] + (r + 4 < NZ ? tb.s10[2] * yv[r + 4] : 0.0);
-          L = g.kappa * (tb.d2 * yv[r + 2] - k2 * sm);
+          L = kappa_r * (tb.d2 * yv[r + 2] - k2 * sm);
         } else if (m == 0) {
-          L = g.nu * tb.d2 * yv[r + 2];
+          L = nu_r * tb.d2 * yv[r + 2];
         } else {
           const double* tv = sY + ((MT + mt) * 2 + (ri ^ 1)) * LD;
           double sa = 0, sb = 0, st5 = 0;
@@ -1354,13 +1386,13 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
               sb += tb.b[t] * yv[r + 2 * t];
               st5 += tb.b[t] * tv[r + 2 * t];
             }
-          L = g.nu * (tb.d4 * yv[r + 4] - 2.0 * k2 * sa + k2 * k2 * sb) + (ri == 0 ? k * st5 : -k * st5);
+          L = nu_r * (tb.d4 * yv[r + 4] - 2.0 * k2 * sa + k2 * k2 * sb) + (ri == 0 ? k * st5 : -k * st5);
         }
         LYhist[(size_t(a.stage - 1) * a.cap + s) * st + goff(c) + r] = L;
       }
     }
     if (a.write_X) {
-      double* Xw = X + size_t(s) * st;
+      double* Xw = const_cast<double*>(Xs);
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
@@ -1891,7 +1923,7 @@ diag_partial_kernel(GridDev g, const double* __restrict__ X, int slot0, int cap,
   __shared__ double red[(kBlock / 64) * 4];
   const int Nz = g.Nz, Mx = g.Mx, MC = diag_modes(Nz);
   const int bpos = blockIdx.x / nchunk, chunk = blockIdx.x - bpos * nchunk;
-  const double* x = X + size_t(ring_slot(bpos, slot0, cap)) * g.state;
+  const double* x = batch_state(g, X, bpos, ring_slot(bpos, slot0, cap));
   const int m0 = chunk * MC, nm = min(MC, Mx - m0);
   double* sP = sd;                      // [MC][re, im][Nz] psi (u_bar at m = 0)
   double* sT = sP + MC * 2 * Nz;        // T
@@ -1957,6 +1989,7 @@ __global__ void diag_final_kernel(GridDev g, const double* __restrict__ X, int s
                                   const SlotMeta* __restrict__ meta, int t, int stride, int nsf, int S) {
   if (threadIdx.x != 0) return;
   const int bpos = blockIdx.x, slot = ring_slot(bpos, slot0, cap);
+  const RunDev* rd = batch_run(g, bpos);
   double* o;
   if (meta) {
     const SlotMeta mt = meta[slot];
@@ -1970,7 +2003,7 @@ __global__ void diag_final_kernel(GridDev g, const double* __restrict__ X, int s
   for (int c = 0; c < nchunk; ++c)
     for (int q = 0; q < 4; ++q) v[q] += part[(size_t(bpos) * nchunk + c) * 4 + q];
   const int Nz = g.Nz;
-  const double* tm = X + size_t(slot) * g.state + size_t(1 * g.Mx + 0) * 2 * Nz;
+  const double* tm = batch_state(g, X, bpos, slot) + size_t(1 * g.Mx + 0) * 2 * Nz;
   double nb = 0, nt = 0, t0 = 0, t1 = 0;
   for (int n = 0; n < Nz; ++n) {
     const double sgn = (n & 1) ? -1.0 : 1.0, n2 = double(n) * n;
@@ -1980,11 +2013,11 @@ __global__ void diag_final_kernel(GridDev g, const double* __restrict__ X, int s
     t1 += tm[n];
   }
   const double ref = (t0 - t1) / g.Lz;           // conductive flux of the mean temperature drop
-  o[0] = ((t0 - t1) / g.Lz + g.sqrtRaPr * v[0]) / ref;   // Nu_V
+  o[0] = ((t0 - t1) / g.Lz + rd->sqrtRaPr * v[0]) / ref;   // Nu_V
   o[1] = -g.scale * nb / ref;                            // Nu_b
   o[2] = -g.scale * nt / ref;                            // Nu_t
   o[3] = 0.5 * (v[1] + v[2]);                    // KE
-  o[4] = g.nu * v[3];                            // epsilon_U
+  o[4] = rd->nu * v[3];                          // epsilon_U
   o[5] = v[0];                                   // P = <w T>
 }
 

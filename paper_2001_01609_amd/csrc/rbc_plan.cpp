@@ -385,9 +385,25 @@ std::string build_plan(GridPlan& g) {
 size_t plan_device_bytes(const GridPlan& g) {
   size_t rb = g.mixed ? 4 : 8;
   size_t d = g.bS10.size() + g.bD2.size() + g.bA.size() + g.bB.size() + g.bD4.size() +
-             g.facT.size() + g.facP.size();
+             g.facT.size() + g.facP.size() + sizeof(RunDev) / 8 + 1;
   size_t r = g.Winv.size() + g.Wfwd.size() + g.tw.size() + g.Winv2.size() + g.Wfwd2.size();
   return d * 8 + r * rb + 64 * 16;
+}
+
+RunDev make_run_dev(const GridPlan& g, const double* facT_dev, const double* facP_dev) {
+  RunDev r{};
+  r.facT = facT_dev;
+  r.facP = facP_dev;
+  r.nu = g.nu;
+  r.kappa = g.kappa;
+  r.sqrtRaPr = std::sqrt(g.Ra * g.Pr);
+  // the stage coefficients as the launchers form them for StageArgs
+  for (int i = 0; i < kMaxStages; ++i)
+    for (int j = 0; j < kMaxStages; ++j) {
+      r.hae[i][j] = g.dt * g.tab.ae[i][j];
+      r.hai[i][j] = g.dt * g.tab.ai[i][j];
+    }
+  return r;
 }
 
 hipError_t upload_plan(GridPlan& g) {
@@ -400,6 +416,8 @@ hipError_t upload_plan(GridPlan& g) {
   auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
   for (auto* v : dbl) { offs.push_back(off); off = align(off + v->size() * 8); }
   for (auto* v : rl) { offs.push_back(off); off = align(off + v->size() * rb); }
+  const size_t run_off = off;   // the grid's own RunDev
+  off = align(off + sizeof(RunDev));
   std::vector<unsigned char> host(off, 0);
   size_t k = 0;
   for (auto* v : dbl) { std::memcpy(host.data() + offs[k++], v->data(), v->size() * 8); }
@@ -413,9 +431,12 @@ hipError_t upload_plan(GridPlan& g) {
   }
   hipError_t e = hipMalloc(&g.d_tables, off);
   if (e != hipSuccess) return e;
+  auto* base = static_cast<unsigned char*>(g.d_tables);
+  const RunDev r0 = make_run_dev(g, reinterpret_cast<const double*>(base + offs[5]),
+                                 reinterpret_cast<const double*>(base + offs[6]));
+  std::memcpy(host.data() + run_off, &r0, sizeof(RunDev));
   e = hipMemcpy(g.d_tables, host.data(), off, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  auto* base = static_cast<unsigned char*>(g.d_tables);
   GridDev& d = g.dev;
   d.Nx = g.Nx; d.Nz = g.Nz; d.Mx = g.Mx; d.Px = g.Px; d.Pz = g.Pz; d.n = g.Nz / 2;
   d.nrT = d.n - 1; d.nrP = d.n - 2; d.MT = g.MT;
@@ -449,6 +470,9 @@ hipError_t upload_plan(GridPlan& g) {
   d.tw = base + offs[9];
   d.Winv2 = g.split ? reinterpret_cast<const float*>(base + offs[10]) : nullptr;
   d.Wfwd2 = g.split ? reinterpret_cast<const float*>(base + offs[11]) : nullptr;
+  d.run0 = reinterpret_cast<const RunDev*>(base + run_off);
+  d.xptrs = nullptr;
+  d.rptrs = nullptr;
   return hipSuccess;
 }
 

@@ -104,6 +104,16 @@ def _load():
         "rbc_get_pipeline_stats": (st, [vp, P(rbc_pipeline_stats)]),
         "rbc_diagnostics_noalloc": (st, [vp, vp, i32, vp]),
         "rbc_get_state": (st, [vp, vp, P(ctypes.c_size_t)]),
+        "rbc_ensemble_create": (st, [vp, P(vp)]),
+        "rbc_ensemble_destroy": (st, [vp]),
+        "rbc_ensemble_last_error": (ctypes.c_char_p, [vp]),
+        "rbc_ensemble_footprint": (st, [P(rbc_params), P(ctypes.c_size_t)]),
+        "rbc_ensemble_add": (st, [vp, P(rbc_params), vp, i32, dbl, P(i32)]),
+        "rbc_ensemble_step": (st, [vp, P(i32)]),
+        "rbc_ensemble_run_info": (st, [vp, i32, P(i32), P(i32), P(i32), P(dbl), i32]),
+        "rbc_ensemble_result": (st, [vp, i32, vp]),
+        "rbc_ensemble_release": (st, [vp, i32]),
+        "rbc_ensemble_run_bytes": (st, [vp, i32, P(ctypes.c_size_t)]),
         "rbc_set_state": (st, [vp, vp, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
@@ -292,3 +302,70 @@ def params_from_workload(w, **overrides) -> rbc_params:
     for k, v in overrides.items():
         setattr(p, k, v)
     return p
+
+
+# ---------------------------------------------------------------- ensembles ---
+
+def _echeck(status: int, e) -> int:
+    if status < 0:
+        msg = _lib.rbc_ensemble_last_error(e) if e else b""
+        raise RbcError(status, msg.decode() if msg else "")
+    return status
+
+
+def rbc_ensemble_create(stream: Optional[int] = None):
+    e = ctypes.c_void_p()
+    _echeck(_lib.rbc_ensemble_create(stream, ctypes.byref(e)), None)
+    return e
+
+
+def rbc_ensemble_destroy(e) -> None:
+    _echeck(_lib.rbc_ensemble_destroy(e), None)
+
+
+def rbc_ensemble_last_error(e) -> str:
+    return (_lib.rbc_ensemble_last_error(e) or b"").decode()
+
+
+def rbc_ensemble_footprint(p: rbc_params) -> int:
+    n = ctypes.c_size_t()
+    _echeck(_lib.rbc_ensemble_footprint(ctypes.byref(p), ctypes.byref(n)), None)
+    return n.value
+
+
+def rbc_ensemble_add(e, p: rbc_params, U0, k_max: int, tol: float) -> int:
+    rid = ctypes.c_int32()
+    _echeck(_lib.rbc_ensemble_add(e, ctypes.byref(p), _ptr(U0), k_max, tol, ctypes.byref(rid)), e)
+    return rid.value
+
+
+def rbc_ensemble_step(e) -> int:
+    n = ctypes.c_int32()
+    _echeck(_lib.rbc_ensemble_step(e, ctypes.byref(n)), e)
+    return n.value
+
+
+ENSEMBLE_ACTIVE, ENSEMBLE_DONE, ENSEMBLE_FAILED, ENSEMBLE_RELEASED = 0, 1, 2, 3
+
+
+def rbc_ensemble_run_info(e, run_id: int, hist_len: int = 0):
+    """(state, k_done, stop, defects[:min(k_done, hist_len)])."""
+    st, k, stop = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    hist = np.zeros(max(hist_len, 1))
+    _echeck(_lib.rbc_ensemble_run_info(e, run_id, ctypes.byref(st), ctypes.byref(k), ctypes.byref(stop),
+                                       hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hist_len), e)
+    return st.value, k.value, stop.value, hist[: min(k.value, hist_len)].copy()
+
+
+def rbc_ensemble_result(e, run_id: int, U) -> None:
+    _echeck(_lib.rbc_ensemble_result(e, run_id, _ptr(U)), e)
+
+
+def rbc_ensemble_release(e, run_id: int) -> None:
+    _echeck(_lib.rbc_ensemble_release(e, run_id), e)
+
+
+def rbc_ensemble_run_bytes(e, run_id: int) -> int:
+    n = ctypes.c_size_t()
+    _echeck(_lib.rbc_ensemble_run_bytes(e, run_id, ctypes.byref(n)), e)
+    return n.value
