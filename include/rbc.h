@@ -171,6 +171,11 @@ rbc_status rbc_steps_per_slice(rbc_handle h, int32_t coarse, int32_t* n_steps, d
  * xi = sqrt(-2 ln(1 - u1)) cos(2 pi u2).  Writes one fine state. */
 rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double noise_amp, double* U0_dev);
 
+/* The same initial state without a handle (for ensemble runs): the fine
+ * state of parameters p into U0_dev, on hip_stream (NULL: the null
+ * stream); synchronises that stream. */
+rbc_status rbc_initial_state(const rbc_params* p, uint64_t seed, double noise_amp, double* U0_dev, void* hip_stream);
+
 /* The fine propagator F on a batch of slices (the data-parallel half of
  * Eq. 19): n_steps IMEX steps of the fine grid on each of n_slices
  * independent states.  U_in and U_out are [n_slices][state] (they may be

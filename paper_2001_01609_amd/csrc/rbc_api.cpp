@@ -165,6 +165,62 @@ void sampling(const rbc_params* p, int nf, int nc, double dtf, double dtc, int* 
 
 }  // namespace
 
+// The seeded initial state of grid g into host memory U (one fine state).
+static void initial_state_host(const rbc::GridPlan& g, uint64_t seed, double amp, std::vector<double>& U_out) {
+  const int Nx = g.Nx, Nz = g.Nz, Mx = g.Mx;
+  // seeded noise: SplitMix64 outputs 2p, 2p+1 -> Box-Muller (cosine branch)
+  auto mix = [seed](uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto unif = [&](uint64_t c) { return double(mix(c) >> 11) * (1.0 / 9007199254740992.0); };
+  std::vector<double> Tg(size_t(Nx) * Nz), zj(Nz);
+  for (int j = 0; j < Nz; ++j) zj[j] = (std::cos(M_PI * (j + 0.5) / Nz) + 1.0) * 0.5;   // z / Lz
+  for (int ix = 0; ix < Nx; ++ix)
+    for (int iz = 0; iz < Nz; ++iz) {
+      const uint64_t pidx = uint64_t(ix) * Nz + iz;
+      const double u1 = unif(2 * pidx), u2 = unif(2 * pidx + 1);
+      const double xi = std::sqrt(-2.0 * std::log(1.0 - u1)) * std::cos(2.0 * M_PI * u2);
+      const double z = zj[iz];
+      const double base = g.flux ? g.T_bot - z * g.Lz : g.T_bot + (g.T_top - g.T_bot) * z;
+      Tg[size_t(ix) * Nz + iz] = base + amp * xi * z * (1.0 - z);
+    }
+  // Fourier in x (modes m < Mx, 1/Nx normalisation), Chebyshev in z
+  std::vector<double> cs(Nx), sn(Nx);
+  for (int t = 0; t < Nx; ++t) {
+    cs[t] = std::cos(2.0 * M_PI * t / Nx);
+    sn[t] = std::sin(2.0 * M_PI * t / Nx);
+  }
+  std::vector<double> U(size_t(4) * Mx * Nz, 0.0), fr(Nz), fi(Nz);
+  std::vector<double> Tc(size_t(Nz) * Nz);
+  for (int n = 0; n < Nz; ++n)
+    for (int j = 0; j < Nz; ++j) Tc[size_t(n) * Nz + j] = (n == 0 ? 1.0 : 2.0) / Nz * std::cos(n * M_PI * (j + 0.5) / Nz);
+  for (int m = 0; m < Mx; ++m) {
+    for (int j = 0; j < Nz; ++j) {
+      double ar = 0, ai = 0;
+      for (int ix = 0; ix < Nx; ++ix) {
+        const int t = int((int64_t(m) * ix) % Nx);
+        ar += Tg[size_t(ix) * Nz + j] * cs[t];
+        ai -= Tg[size_t(ix) * Nz + j] * sn[t];
+      }
+      fr[j] = ar / Nx;
+      fi[j] = (m == 0) ? 0.0 : ai / Nx;
+    }
+    for (int n = 0; n < Nz; ++n) {
+      double cr = 0, ci = 0;
+      for (int j = 0; j < Nz; ++j) {
+        cr += Tc[size_t(n) * Nz + j] * fr[j];
+        ci += Tc[size_t(n) * Nz + j] * fi[j];
+      }
+      U[((size_t(1) * Mx + m) * 2 + 0) * Nz + n] = cr;
+      U[((size_t(1) * Mx + m) * 2 + 1) * Nz + n] = ci;
+    }
+  }
+  U_out.swap(U);
+}
+
 namespace rbc {
 
 // The fine and coarse plans of one run, built and uploaded as rbc_create
@@ -365,60 +421,27 @@ rbc_status rbc_steps_per_slice(rbc_handle h, int32_t coarse, int32_t* n_steps, d
 
 rbc_status rbc_init_state(rbc_handle h, uint64_t seed, double amp, double* U0) {
   if (!h || !U0) return fail(h, RBC_ERR_ARG, "null argument");
-  const rbc::GridPlan& g = h->fine;
-  const int Nx = g.Nx, Nz = g.Nz, Mx = g.Mx;
-  // seeded noise: SplitMix64 outputs 2p, 2p+1 -> Box-Muller (cosine branch)
-  auto mix = [seed](uint64_t c) {
-    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-  };
-  auto unif = [&](uint64_t c) { return double(mix(c) >> 11) * (1.0 / 9007199254740992.0); };
-  std::vector<double> Tg(size_t(Nx) * Nz), zj(Nz);
-  for (int j = 0; j < Nz; ++j) zj[j] = (std::cos(M_PI * (j + 0.5) / Nz) + 1.0) * 0.5;   // z / Lz
-  for (int ix = 0; ix < Nx; ++ix)
-    for (int iz = 0; iz < Nz; ++iz) {
-      const uint64_t pidx = uint64_t(ix) * Nz + iz;
-      const double u1 = unif(2 * pidx), u2 = unif(2 * pidx + 1);
-      const double xi = std::sqrt(-2.0 * std::log(1.0 - u1)) * std::cos(2.0 * M_PI * u2);
-      const double z = zj[iz];
-      const double base = g.flux ? g.T_bot - z * g.Lz : g.T_bot + (g.T_top - g.T_bot) * z;
-      Tg[size_t(ix) * Nz + iz] = base + amp * xi * z * (1.0 - z);
-    }
-  // Fourier in x (modes m < Mx, 1/Nx normalisation), Chebyshev in z
-  std::vector<double> cs(Nx), sn(Nx);
-  for (int t = 0; t < Nx; ++t) {
-    cs[t] = std::cos(2.0 * M_PI * t / Nx);
-    sn[t] = std::sin(2.0 * M_PI * t / Nx);
-  }
-  std::vector<double> U(size_t(4) * Mx * Nz, 0.0), fr(Nz), fi(Nz);
-  std::vector<double> Tc(size_t(Nz) * Nz);
-  for (int n = 0; n < Nz; ++n)
-    for (int j = 0; j < Nz; ++j) Tc[size_t(n) * Nz + j] = (n == 0 ? 1.0 : 2.0) / Nz * std::cos(n * M_PI * (j + 0.5) / Nz);
-  for (int m = 0; m < Mx; ++m) {
-    for (int j = 0; j < Nz; ++j) {
-      double ar = 0, ai = 0;
-      for (int ix = 0; ix < Nx; ++ix) {
-        const int t = int((int64_t(m) * ix) % Nx);
-        ar += Tg[size_t(ix) * Nz + j] * cs[t];
-        ai -= Tg[size_t(ix) * Nz + j] * sn[t];
-      }
-      fr[j] = ar / Nx;
-      fi[j] = (m == 0) ? 0.0 : ai / Nx;
-    }
-    for (int n = 0; n < Nz; ++n) {
-      double cr = 0, ci = 0;
-      for (int j = 0; j < Nz; ++j) {
-        cr += Tc[size_t(n) * Nz + j] * fr[j];
-        ci += Tc[size_t(n) * Nz + j] * fi[j];
-      }
-      U[((size_t(1) * Mx + m) * 2 + 0) * Nz + n] = cr;
-      U[((size_t(1) * Mx + m) * 2 + 1) * Nz + n] = ci;
-    }
-  }
+  std::vector<double> U;
+  initial_state_host(h->fine, seed, amp, U);
   HIPCHK(h, hipMemcpyAsync(U0, U.data(), U.size() * 8, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RBC_OK;
+}
+
+rbc_status rbc_initial_state(const rbc_params* p, uint64_t seed, double amp, double* U0, void* hip_stream) {
+  if (!p || !U0) return fail(nullptr, RBC_ERR_ARG, "null argument");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(nullptr, RBC_ERR_ARG, e);
+  rbc::GridPlan g;
+  double dtf;
+  steps_for(p->t0, p->t_end, p->n_slices, p->dt_f, &dtf);
+  setup_grid(g, p, false, dtf);
+  std::vector<double> U;
+  initial_state_host(g, seed, amp, U);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t he = hipMemcpyAsync(U0, U.data(), U.size() * 8, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return fail(nullptr, RBC_ERR_HIP, std::string("rbc_initial_state: ") + hipGetErrorString(he));
   return RBC_OK;
 }
 

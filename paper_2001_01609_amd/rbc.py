@@ -104,6 +104,7 @@ def _load():
         "rbc_get_pipeline_stats": (st, [vp, P(rbc_pipeline_stats)]),
         "rbc_diagnostics_noalloc": (st, [vp, vp, i32, vp]),
         "rbc_get_state": (st, [vp, vp, P(ctypes.c_size_t)]),
+        "rbc_initial_state": (st, [P(rbc_params), ctypes.c_uint64, dbl, vp, vp]),
         "rbc_ensemble_create": (st, [vp, P(vp)]),
         "rbc_ensemble_destroy": (st, [vp]),
         "rbc_ensemble_last_error": (ctypes.c_char_p, [vp]),
@@ -183,6 +184,10 @@ def rbc_steps_per_slice(h, coarse: int = 0) -> Tuple[int, float]:
 
 def rbc_init_state(h, seed: int, noise_amp: float, U0) -> None:
     _check(_lib.rbc_init_state(h, seed, noise_amp, _ptr(U0)), h)
+
+
+def rbc_initial_state(p: rbc_params, seed: int, noise_amp: float, U0, stream: Optional[int] = None) -> None:
+    _check(_lib.rbc_initial_state(ctypes.byref(p), seed, noise_amp, _ptr(U0), stream))
 
 
 def rbc_fine_step_batch(h, U_in, U_out, n_slices: int, n_steps: int, nu_samples=None) -> None:

@@ -99,3 +99,28 @@ C3 = Workload("ra1e8_1024x256_s64_ars443_mixed", 1e8, 1.0, 2.0, 1.0, 1024, 256, 
               0.0, 20.0, 64, 2e-5, 2e-4, 4, True, k_max=10, tol=0.0)
 
 WORKLOADS = {w.name: w for w in (C1, C2, C2_FP64, C3)}
+
+
+# Ensemble of independent runs: 24 runs, run i with its own seed 4000 + i,
+# Ra log-uniform in [1e5, 1e7], fine grid uniform over {128x32, 256x64,
+# 512x128} restricted to the grids that resolve Ra (above 1e6: at least
+# 256x64), coarse grid half the fine one in each direction, fine step
+# 1e-4 * 64 / Nz, coarse step ten times that, 16 slices each, mixed
+# precision.  The horizon is a parameter (the runs' length, not their
+# shape, sets the cost).
+ENSEMBLE_GRIDS = ((128, 32), (256, 64), (512, 128))
+
+
+def ensemble_runs(n_runs: int = 24, t_end: float = 10.0, n_slices: int = 16, seed0: int = 4000):
+    """The runs of the ensemble workload as Workloads (name, Ra, grids,
+    steps, slices), drawn from each run's own seed."""
+    runs = []
+    for i in range(n_runs):
+        u = uniform53(seed0 + i, np.arange(2, dtype=np.uint64))
+        Ra = 10.0 ** (5.0 + 2.0 * u[0])
+        grids = [g for g in ENSEMBLE_GRIDS if Ra <= 1e6 or g[1] >= 64]
+        Nx, Nz = grids[min(int(u[1] * len(grids)), len(grids) - 1)]
+        dt = 1e-4 * 64 / Nz
+        runs.append(Workload(f"ensemble_run{i}", Ra, 1.0, 2.0, 1.0, Nx, Nz, Nx // 2, Nz // 2, 0.0, t_end, n_slices,
+                             dt, 10 * dt, 4, True, seed=seed0 + i, k_max=n_slices, tol=1e-8))
+    return runs
