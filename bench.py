@@ -25,6 +25,11 @@ right-hand-side history, stage writes).  The whole step's 896 bytes per
 DOF-step is reported beside it, with the x-pass.
 
 Legs beside the headline (skippable):
+  ensemble          24 independent runs of different Rayleigh numbers and
+                    grids (128 x 32, 256 x 64, 512 x 128; 16 slices each)
+                    advanced together by the ensemble engine;
+  serving           a Poisson stream of Parareal requests served with
+                    continuous batching (throughput, p50 / p99 latency);
   parareal_c2       one pipelined Parareal run at Ra 1e6, 256 x 64, 32
                     slices (coarse prediction + 3 iterations) and the same
                     run in the sweep-then-batch order (bit-identical);
@@ -274,6 +279,96 @@ def parareal_leg(w, K: int):
     return out
 
 
+def ensemble_leg(t_end: float = 0.5, k_max: int = 3):
+    """The 24-run ensemble (Ra log-uniform in [1e5, 1e7], grids 128x32 /
+    256x64 / 512x128, 16 slices each, mixed precision) advanced together to
+    k_max iterations: aggregate fine DOF-steps per second of the whole
+    job (predictions and coarse sweeps included)."""
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+    runs = I.ensemble_runs(t_end=t_end)
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev).cuda_stream
+    e = R.rbc_ensemble_create(st)
+    try:
+        ids, plist = [], []
+        t_setup = time.perf_counter()
+        for w in runs:
+            p = R.params_from_workload(w, promote_fp64=0, pipelined=0)
+            U0 = torch.zeros(4 * (w.Nx // 2) * w.Nz, dtype=torch.float64, device=dev)
+            R.rbc_initial_state(p, w.seed, w.noise_amp, U0, st)
+            ids.append(R.rbc_ensemble_add(e, p, U0, k_max, w.tol))
+            plist.append(p)
+        t_setup = time.perf_counter() - t_setup
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        t0 = time.perf_counter()
+        n_steps = 0
+        while R.rbc_ensemble_step(e) > 0:
+            n_steps += 1
+        n_steps += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dof_steps = 0.0
+        for w, rid in zip(runs, ids):
+            _, kd, _, _ = R.rbc_ensemble_run_info(e, rid, 0)
+            nf = math.ceil((w.t_end - w.t0) / w.n_slices / w.dt_f - 1e-9)
+            dof_steps += w.Nx * w.Nz * nf * sum(w.n_slices - k + 1 for k in range(1, kd + 1))
+    finally:
+        R.rbc_ensemble_destroy(e)
+    grids = {}
+    for w in runs:
+        grids[f"{w.Nx}x{w.Nz}"] = grids.get(f"{w.Nx}x{w.Nz}", 0) + 1
+    log(f"ensemble leg: {len(runs)} runs, {n_steps} engine steps in {el:.2f} s")
+    return {"runs": len(runs), "grids": grids, "slices_per_run": runs[0].n_slices, "t": [0.0, t_end],
+            "iterations": k_max, "engine_steps": n_steps, "s": el, "setup_s": t_setup,
+            "fine_dof_steps": dof_steps, "fine_dof_steps_per_s": dof_steps / el,
+            "device_bytes_free_at_start": free0}
+
+
+def serving_leg(n: int = 24, rate: float = 2.0, seed: int = 5000):
+    """A Poisson stream of Parareal requests (Ra log-uniform in [1e4, 1e7],
+    grids 64x32 .. 512x128, horizons in [0.05, 0.3], tolerance 1e-6 (mixed)
+    or 1e-8 (FP64), 16 slices, at most 3 iterations) served with continuous
+    batching and admission by free device memory."""
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+    from paper_2001_01609_amd import serving as SV
+    descs = SV.request_stream(n, rate, seed=seed)
+    reqs = [SV.Request(rid=d["rid"], arrival=d["arrival"], params=SV.make_params(R, d), seed=d["seed"],
+                       tol=d["tol"], k_max=d["k_max"]) for d in descs]
+    eng = SV.GpuEngine()
+    free_min = [torch.cuda.mem_get_info()[0]]
+    total = torch.cuda.mem_get_info()[1]
+
+    def free():
+        f = torch.cuda.mem_get_info()[0]
+        free_min[0] = min(free_min[0], f)
+        return f
+
+    sched = SV.Scheduler(eng, free_bytes=free, footprint=lambda q: R.rbc_ensemble_footprint(q.params),
+                         reserve=8 << 30, max_active=16)
+    try:
+        wall = SV.serve(reqs, sched)
+    finally:
+        eng.close()
+    rep = SV.latency_report(sched.done, wall)
+    dof = 0.0
+    for c in sched.done:
+        d = descs[c.rid]
+        nf = math.ceil(d["t_end"] / d["n_slices"] / d["dt_f"] - 1e-9)
+        dof += d["Nx"] * d["Nz"] * nf * sum(d["n_slices"] - k + 1 for k in range(1, c.k_done + 1))
+    rep.update({"arrival_rate_per_s": rate, "engine_steps": sched.steps, "peak_active_runs": sched.peak_active,
+                "fine_dof_steps_per_s": dof / wall, "peak_device_bytes_used": int(total - free_min[0]),
+                "admission_waits": sched.admission_waits,
+                "failed": sum(1 for c in sched.done if c.state != 1)})
+    log(f"serving leg: {rep['requests']} requests in {wall:.2f} s, p50 {rep['latency_p50_s']:.2f} s, "
+        f"p99 {rep['latency_p99_s']:.2f} s")
+    return rep
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +378,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution leg")
     ap.add_argument("--no-parareal", action="store_true", help="skip the Parareal throughput leg")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 24-run ensemble leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
                     help="counter-collection mode: only N batched fine steps of the headline (same kernels "
                          "and launch shapes), no JSON line")
@@ -405,6 +502,10 @@ def main() -> int:
         out["parareal_c2"] = parareal_leg(I.C2, 3)
     if not args.no_tts:
         out["time_to_solution"] = time_to_solution(I.C2)
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_leg()
+    if not args.no_serving:
+        out["serving"] = serving_leg()
     if args.cpu_seconds > 0:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
