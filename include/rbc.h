@@ -134,6 +134,23 @@ typedef struct {
 /* Fill p with defaults (T_bot = 1, T_top = 0, ARS443, FP64, no sampling). */
 rbc_status rbc_default_params(rbc_params* p);
 
+/* Measured launch shapes (autotuning).  rbc_tuning_load reads a text
+ * table, one entry per line ('#' starts a comment):
+ *     role precision Nx Nz slices MT split xrows
+ * role "fine" or "coarse", precision "mixed" or "fp64", the grid, the batch
+ * (slices per launch: n_slices for fine plans, 1 for coarse), and the
+ * choice: modes per block of the per-mode kernel (2, 4, 6, 8), 1 = the
+ * split path (mixed fine grids with Nz >= 64 and Nx >= 128 only), x-pass
+ * rows per block (1, 2, 4; 0 = by rule).  Later rbc_create calls use the
+ * entry of the same role, precision and grid whose batch is nearest, in
+ * place of the built-in rules (the environment variables RBC_MODE_TILE,
+ * RBC_SPLIT, RBC_XPASS_ROWS still override).  The choice changes launch
+ * shapes only, never a result beyond rounding order.  NULL clears the
+ * table; the table is process-wide.  The Python binding loads the table
+ * measured for gfx950 at import. */
+rbc_status rbc_tuning_load(const char* path);
+rbc_status rbc_tuning_entries(int32_t* n_entries);
+
 /* Device bytes rbc_create would allocate for p (admission control). */
 rbc_status rbc_query_footprint(const rbc_params* p, size_t* device_bytes);
 

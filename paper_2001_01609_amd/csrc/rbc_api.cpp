@@ -6,7 +6,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -30,6 +33,32 @@ namespace {
 
 using rbc::fail;
 #define HIPCHK RBC_HIPCHK
+
+// Tuning table (rbc_tuning_load): measured launch shapes per role (fine or
+// coarse plan), precision, grid and batch size.
+struct TuneEntry {
+  int coarse, mixed, Nx, Nz, slices;
+  int MT, split, xrows;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+// The entry for this role, precision and grid whose batch is nearest (in
+// ratio) to `slices`, or null.
+const TuneEntry* tune_lookup(bool coarse, bool mixed, int Nx, int Nz, int slices) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const TuneEntry* best = nullptr;
+  double bd = 0;
+  for (const TuneEntry& t : g_tune) {
+    if (t.coarse != int(coarse) || t.mixed != int(mixed) || t.Nx != Nx || t.Nz != Nz) continue;
+    const double d = std::fabs(std::log(double(std::max(t.slices, 1)) / std::max(slices, 1)));
+    if (!best || d < bd) {
+      best = &t;
+      bd = d;
+    }
+  }
+  return best;
+}
 
 int steps_for(double t0, double t1, int S, double dt, double* dt_used) {
   const double dT = (t1 - t0) / S;
@@ -91,9 +120,26 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   // (the single-slice coarse grid and single-run fine batches are latency-bound:
   // small tiles, more blocks)
   g.MT = (coarse || g.Nz >= 128 || p->n_slices <= 2) ? 2 : 4;
+  // split path (the Chebyshev transforms as FP32 MFMA GEMMs over the whole
+  // batch): by rule for mixed-precision fine grids with Nz >= 128
+  const bool split_grid = g.mixed && !coarse && g.Nz >= 64 && g.Mx % 64 == 0;
+  g.split = split_grid && g.Nz >= 128 && g.MT <= 4;
+  g.xrows = 0;
+  // a measured choice for this role, precision, grid and batch (rbc_tuning_load)
+  if (const TuneEntry* t = tune_lookup(coarse, g.mixed, g.Nx, g.Nz, coarse ? 1 : p->n_slices)) {
+    g.MT = t->MT;
+    g.split = split_grid && t->split && t->MT <= 4;
+    g.xrows = t->xrows;
+  }
+  // measurement overrides: RBC_MODE_TILE, RBC_SPLIT, RBC_XPASS_ROWS
   if (const char* e = std::getenv("RBC_MODE_TILE")) {
     const int v = std::atoi(e);
     if (v == 2 || v == 4 || v == 6 || v == 8) g.MT = v;
+  }
+  if (const char* e = std::getenv("RBC_SPLIT")) g.split = split_grid && std::atoi(e) != 0;
+  if (const char* e = std::getenv("RBC_XPASS_ROWS")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) g.xrows = v;
   }
   if (g.MT > g.Mx) g.MT = g.Mx;   // Mx is a power of two >= 2
   // keep the per-mode kernel's LDS (two FP64 tiles + staged factors) < 150 KiB
@@ -106,12 +152,7 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
     return y + (y + u > v ? y + u : v);
   };
   while (g.MT > 2 && lds(g.MT) > 150 * 1024) g.MT = (g.MT == 6) ? 4 : g.MT / 2;
-  // Split path (the Chebyshev transforms as FP32 MFMA GEMMs over the whole
-  // batch): mixed-precision fine grids with Nz >= 128; RBC_SPLIT = 0 / 1
-  // overrides where the grid allows it (Nz >= 64, Nx >= 128, MT <= 4).
-  const bool split_ok = g.mixed && !coarse && g.Nz >= 64 && g.Mx % 64 == 0 && g.MT <= 4;
-  g.split = split_ok && g.Nz >= 128;
-  if (const char* e = std::getenv("RBC_SPLIT")) g.split = split_ok && std::atoi(e) != 0;
+  if (g.MT > 4) g.split = false;   // the split path's per-mode kernel takes tiles of 2 or 4
 }
 
 size_t pararea_bytes(const rbc_params* p, const rbc::GridPlan& f, const rbc::GridPlan& c, int nsf, int nsc) {
@@ -280,6 +321,43 @@ rbc_status rbc_default_params(rbc_params* p) {
   p->promote_fp64 = 1;
   p->pipelined = 1;
   p->stat_tol = 0;
+  return RBC_OK;
+}
+
+rbc_status rbc_tuning_load(const char* path) {
+  std::vector<TuneEntry> tab;
+  if (path) {
+    std::ifstream in(path);
+    if (!in) return fail(nullptr, RBC_ERR_ARG, std::string("cannot open tuning table ") + path);
+    std::string line;
+    int ln = 0;
+    while (std::getline(in, line)) {
+      ++ln;
+      const size_t hash = line.find('#');
+      if (hash != std::string::npos) line.resize(hash);
+      std::istringstream ss(line);
+      std::string role, prec;
+      TuneEntry t{};
+      if (!(ss >> role)) continue;
+      if (!(ss >> prec >> t.Nx >> t.Nz >> t.slices >> t.MT >> t.split >> t.xrows) ||
+          (role != "fine" && role != "coarse") || (prec != "mixed" && prec != "fp64") ||
+          (t.MT != 2 && t.MT != 4 && t.MT != 6 && t.MT != 8) || (t.xrows != 0 && t.xrows != 1 && t.xrows != 2 &&
+                                                                 t.xrows != 4))
+        return fail(nullptr, RBC_ERR_ARG, std::string(path) + ":" + std::to_string(ln) + ": bad tuning entry");
+      t.coarse = role == "coarse";
+      t.mixed = prec == "mixed";
+      tab.push_back(t);
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.swap(tab);
+  return RBC_OK;
+}
+
+rbc_status rbc_tuning_entries(int32_t* n) {
+  if (!n) return RBC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *n = int32_t(g_tune.size());
   return RBC_OK;
 }
 

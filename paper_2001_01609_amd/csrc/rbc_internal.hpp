@@ -68,6 +68,7 @@ struct GridDev {
   int XT, nxt;                    // mode tile of the mixed-space arrays (tile-major) and their count:
                                   // XT = MT in the fused path, kGemmModes in the split path
   int split;                      // 1: split path (transforms as FP32 MFMA GEMMs, see fwd_gemm_kernel)
+  int xrows;                      // x-pass rows per block (1, 2, 4), 0: by rule
   int state;                      // doubles per state = 4 Mx Nz
   double kscale;                  // k_m = m * kscale
   double nu, kappa, scale;        // viscosity, diffusivity, dzeta/dz = 2/Lz
@@ -117,6 +118,7 @@ struct GridPlan {
   // over every column of the launch (fwd_gemm_kernel, inv_gemm_kernel)
   // around the per-mode solve kernel, instead of inside it.
   bool split = false;
+  int xrows = 0;                  // x-pass rows per block (tuned), 0: by rule
   // host tables
   std::vector<double> bS10, bD2, bA, bB, bD4, facT, facP, Winv, Wfwd, tw, Winv2, Wfwd2;
 

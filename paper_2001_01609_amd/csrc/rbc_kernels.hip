@@ -2205,22 +2205,36 @@ constexpr int xpass_rows() {
   return (4 * row <= 80 * 1024) ? 4 : ((2 * row <= 80 * 1024) ? 2 : 1);
 }
 
+template <typename Real, int PX, int RB>
+hipError_t launch_xpass_rb(const GridDev& d, Work& w, int slot0, int n_slices, hipStream_t st) {
+  const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, RB>() * size_t(PX) * RB;
+  hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(xcd_grid(d.one_xcd, n_slices * (d.Pz / RB))), dim3(64 * RB),
+                     lds, st, d, (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
+  return hipGetLastError();
+}
+
+template <typename Real, int PX, int RB>
+constexpr bool xpass_rows_fit() {
+  return sizeof(Real) * 2 * xpass_spectra<Real, PX, RB>() * size_t(PX) * RB <= 160 * 1024;
+}
+
 template <typename Real, int PX>
 hipError_t run_xpass_t(const GridPlan& g, Work& w, int slot0, int n_slices, hipStream_t st) {
   const GridDev& d = g.dev;
-  constexpr int RB = xpass_rows<Real, PX>();
-  // a small batch (the single-slice coarse sweep) would leave most CUs idle
-  // with several rows per block: one row per block there
-  if (RB > 1 && n_slices * (d.Pz / RB) < 256) {
-    const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, 1>() * size_t(PX);
-    hipLaunchKernelGGL((xpass_kernel<Real, PX, 1>), dim3(xcd_grid(d.one_xcd, n_slices * d.Pz)), dim3(64), lds, st,
-                       d, (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
-  } else {
-    const size_t lds = sizeof(Real) * 2 * xpass_spectra<Real, PX, RB>() * size_t(PX) * RB;
-    hipLaunchKernelGGL((xpass_kernel<Real, PX, RB>), dim3(xcd_grid(d.one_xcd, n_slices * (d.Pz / RB))),
-                       dim3(64 * RB), lds, st, d, (const Real*)w.Q, (Real*)w.Nh, (Real*)w.qbar, slot0, w.cap);
+  int rb = d.xrows;   // tuned rows per block, 0: by rule
+  if (rb != 1 && rb != 2 && rb != 4) {
+    rb = xpass_rows<Real, PX>();
+    // a small batch (the single-slice coarse sweep) would leave most CUs
+    // idle with several rows per block: one row per block there
+    if (rb > 1 && n_slices * (d.Pz / rb) < 256) rb = 1;
   }
-  return hipGetLastError();
+  if (rb == 4 && !xpass_rows_fit<Real, PX, 4>()) rb = 2;
+  if (rb == 2 && !xpass_rows_fit<Real, PX, 2>()) rb = 1;
+  if constexpr (xpass_rows_fit<Real, PX, 4>())
+    if (rb == 4) return launch_xpass_rb<Real, PX, 4>(d, w, slot0, n_slices, st);
+  if constexpr (xpass_rows_fit<Real, PX, 2>())
+    if (rb == 2) return launch_xpass_rb<Real, PX, 2>(d, w, slot0, n_slices, st);
+  return launch_xpass_rb<Real, PX, 1>(d, w, slot0, n_slices, st);
 }
 
 template <typename Real>

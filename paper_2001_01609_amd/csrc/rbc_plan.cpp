@@ -442,6 +442,7 @@ hipError_t upload_plan(GridPlan& g) {
   d.nrT = d.n - 1; d.nrP = d.n - 2; d.MT = g.MT;
   d.ntile = (g.Mx + g.MT - 1) / g.MT;
   d.split = g.split ? 1 : 0;
+  d.xrows = g.xrows;
   d.XT = g.split ? kGemmModes : g.MT;
   d.nxt = (g.Mx + d.XT - 1) / d.XT;
   d.state = 4 * g.Mx * g.Nz;

@@ -105,6 +105,8 @@ def _load():
         "rbc_diagnostics_noalloc": (st, [vp, vp, i32, vp]),
         "rbc_get_state": (st, [vp, vp, P(ctypes.c_size_t)]),
         "rbc_initial_state": (st, [P(rbc_params), ctypes.c_uint64, dbl, vp, vp]),
+        "rbc_tuning_load": (st, [ctypes.c_char_p]),
+        "rbc_tuning_entries": (st, [P(i32)]),
         "rbc_ensemble_create": (st, [vp, P(vp)]),
         "rbc_ensemble_destroy": (st, [vp]),
         "rbc_ensemble_last_error": (ctypes.c_char_p, [vp]),
@@ -125,6 +127,23 @@ def _load():
 
 
 _lib = _load()
+
+# launch shapes measured on gfx950 (paper_2001_01609_amd/tune.py writes it)
+TUNING_TABLE = os.path.join(_HERE, "tuning_gfx950.txt")
+
+
+def rbc_tuning_load(path: Optional[str]) -> None:
+    _check(_lib.rbc_tuning_load(path.encode() if path else None))
+
+
+def rbc_tuning_entries() -> int:
+    n = ctypes.c_int32()
+    _check(_lib.rbc_tuning_entries(ctypes.byref(n)))
+    return n.value
+
+
+if os.path.exists(TUNING_TABLE) and not os.environ.get("RBC_NO_TUNING"):
+    rbc_tuning_load(TUNING_TABLE)
 
 
 def _check(status: int, h=None) -> int:

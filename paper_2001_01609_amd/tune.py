@@ -1,0 +1,165 @@
+"""Autotuner of the launch shapes: measures, on the GPU, the candidate
+shapes of each plan the workloads use and writes the fastest into the
+tuning table that the library reads at handle creation (rbc_tuning_load).
+
+Tunables per (role, precision, grid, batch):
+  MT     modes per block of the per-mode kernel (2, 4, 8);
+  split  the split path (Chebyshev transforms as FP32 MFMA GEMMs over the
+         whole batch, mixed fine grids with Nz >= 64, Nx >= 128) or the
+         fused per-mode kernel;
+  xrows  x-pass rows per block (1, 2, 4).
+MT and split are chosen first with the x-pass by rule, then the x-pass rows
+with that choice.  Fine plans are timed as batched fine steps of the batch
+(HIP events around rbc_fine_step_batch), coarse plans as the serial coarse
+prediction sweep (rbc_coarse_sweep).  Each candidate's time and the rule's
+are written beside the entry.
+
+    python -m paper_2001_01609_amd.tune --out paper_2001_01609_amd/tuning_gfx950.txt
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# (role, precision, Nx, Nz, batch as looked up, batch measured, Ra, dt, coarse grid, note)
+TARGETS = [
+    ("fine", "mixed", 1024, 256, 64, 64, 1e8, 2e-5, (256, 64), "1024x256, 64 slices (batched fine step)"),
+    ("fine", "mixed", 256, 64, 32, 32, 1e6, 2e-4, (128, 32), "256x64, 32 slices (Parareal fine runs)"),
+    ("fine", "fp64", 256, 64, 32, 32, 1e6, 2e-4, (128, 32), "256x64, 32 slices, FP64 (promoted fine runs)"),
+    ("fine", "fp64", 256, 64, 1, 1, 1e6, 2e-4, (128, 32), "256x64 serial FP64 stepper"),
+    ("fine", "fp64", 1024, 256, 1, 1, 1e8, 2e-5, (256, 64), "1024x256 serial FP64 stepper"),
+    ("fine", "mixed", 128, 32, 16, 64, 3e5, 2e-4, (64, 16), "ensemble class 128x32 (measured at 64 slices)"),
+    ("fine", "mixed", 256, 64, 16, 176, 2e6, 1e-4, (128, 32), "ensemble class 256x64 (measured at 176 slices)"),
+    ("fine", "mixed", 512, 128, 16, 144, 5e6, 5e-5, (256, 64), "ensemble class 512x128 (measured at 144 slices)"),
+    ("coarse", "mixed", 128, 32, 1, 1, 1e6, 2e-3, None, "coarse sweep 128x32 (256x64 runs)"),
+    ("coarse", "fp64", 128, 32, 1, 1, 1e6, 2e-3, None, "coarse sweep 128x32, FP64"),
+    ("coarse", "mixed", 256, 64, 1, 1, 1e8, 2e-4, None, "coarse sweep 256x64 (1024x256 runs)"),
+]
+
+
+def _params(R, role, prec, Nx, Nz, S, Ra, dt, cgrid):
+    p = R.rbc_default_params()
+    p.Ra, p.Pr, p.Lx, p.Lz = Ra, 1.0, 2.0, 1.0
+    if role == "fine":
+        p.Nx, p.Nz = Nx, Nz
+        p.Nx_c, p.Nz_c = cgrid
+        p.n_slices = S
+        p.dt_f, p.dt_c = dt, 10 * dt
+        p.t_end = dt * 1000 * S
+    else:   # the coarse grid of a run with twice its size, 8 slices of 40 coarse steps
+        p.Nx, p.Nz = 2 * Nx, 2 * Nz
+        p.Nx_c, p.Nz_c = Nx, Nz
+        p.n_slices = 8
+        p.dt_f, p.dt_c = dt / 10, dt
+        p.t_end = dt * 40 * 8
+    p.precision = R.RBC_MIXED if prec == "mixed" else R.RBC_FP64
+    p.promote_fp64 = 0
+    p.pipelined = 0
+    return p
+
+
+def measure(R, torch, target, env):
+    """Mean ms per fine step (fine) or per coarse sweep (coarse) with the
+    shape overrides `env` (RBC_* variables read at handle creation)."""
+    role, prec, Nx, Nz, _, S, Ra, dt, cgrid, _ = target
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        p = _params(R, role, prec, Nx, Nz, S, Ra, dt, cgrid)
+        dev = torch.device("cuda:0")
+        st = torch.cuda.current_stream(dev)
+        h = R.rbc_create(p, st.cuda_stream)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        n = R.rbc_state_size(h, 0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if role == "fine":
+            U = torch.zeros(S * n, dtype=torch.float64, device=dev)
+            R.rbc_init_state(h, 0, 0.1, U[:n])
+            U.view(S, n)[1:] = U.view(S, n)[0]
+            R.rbc_fine_step_batch(h, U, U, S, 3)
+            e0.record(st)
+            R.rbc_fine_step_batch(h, U, U, S, 1)
+            e1.record(st)
+            torch.cuda.synchronize()
+            one = e0.elapsed_time(e1)
+            k = max(5, min(400, int(60.0 / max(one, 1e-3))))
+            e0.record(st)
+            R.rbc_fine_step_batch(h, U, U, S, k)
+            e1.record(st)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / k
+        U = torch.zeros((p.n_slices + 1) * n, dtype=torch.float64, device=dev)
+        R.rbc_init_state(h, 0, 0.1, U)
+        cs = R.rbc_state_size(h, 1)
+        G = torch.zeros(p.n_slices * cs, dtype=torch.float64, device=dev)
+        R.rbc_coarse_sweep(h, 0, 0, U, None, G)
+        e0.record(st)
+        R.rbc_coarse_sweep(h, 0, 0, U, None, G)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    finally:
+        R.rbc_destroy(h)
+
+
+def tune(out_path: str, log=print):
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+    R.rbc_tuning_load(None)   # rules only while measuring
+    lines = ["# Launch shapes measured on gfx950 by paper_2001_01609_amd/tune.py:",
+             "#   python -m paper_2001_01609_amd.tune --out paper_2001_01609_amd/tuning_gfx950.txt",
+             "# role precision Nx Nz slices MT split xrows   # ms per fine step / coarse sweep: rule -> tuned"]
+    for t in TARGETS:
+        role, prec, Nx, Nz, slices, S, _, _, _, note = t
+        split_ok = role == "fine" and prec == "mixed" and Nz >= 64 and Nx >= 128
+        base = measure(R, torch, t, {})
+        cands = [{"RBC_MODE_TILE": mt, "RBC_SPLIT": 0} for mt in (2, 4, 8)]
+        if split_ok:
+            cands += [{"RBC_MODE_TILE": mt, "RBC_SPLIT": 1} for mt in (2, 4)]
+        res = []
+        for c in cands:
+            try:
+                res.append((measure(R, torch, t, c), c))
+            except R.RbcError as e:
+                log(f"  {note}: {c} failed: {e}")
+        best_ms, best = min(res, key=lambda x: x[0])
+        xres = []
+        for xr in (1, 2, 4):
+            c = dict(best, RBC_XPASS_ROWS=xr)
+            xres.append((measure(R, torch, t, c), c))
+        xbest_ms, xbest = min(xres, key=lambda x: x[0])
+        if xbest_ms < best_ms:
+            best_ms, best = xbest_ms, xbest
+        log(f"{note}: rule {base:.4f} ms, tuned {best_ms:.4f} ms with {best}; candidates "
+            + ", ".join(f"{c} {m:.4f}" for m, c in res + xres))
+        lines.append(f"{role} {prec} {Nx} {Nz} {slices} {best['RBC_MODE_TILE']} {best['RBC_SPLIT']} "
+                     f"{best.get('RBC_XPASS_ROWS', 0)}   # {note}: {base:.4f} -> {best_ms:.4f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return lines
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.txt"))
+    args = ap.parse_args()
+    for line in tune(args.out, log=lambda m: print(m, flush=True)):
+        print(line)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -87,3 +87,31 @@ def test_footprint_scales_with_slices():
     # the large workload stays far below one GPU's 288 GB
     c = R.rbc_query_footprint(R.params_from_workload(I.C3))
     assert c < 16e9
+
+
+def test_tuning_table_parses_and_steers_plans(tmp_path):
+    """rbc_tuning_load: a valid table changes the plan the footprint query
+    builds (here: the split path for the 256x64 mixed fine grid), a bad line
+    is rejected with its line number, NULL clears."""
+    import rbc_inputs as I
+    from paper_2001_01609_amd import rbc as R
+    p = R.params_from_workload(I.C2)
+    R.rbc_tuning_load(None)
+    assert R.rbc_tuning_entries() == 0
+    base = R.rbc_query_footprint(p)
+    good = tmp_path / "t.txt"
+    good.write_text("# comment\nfine mixed 256 64 32 2 1 0   # split, two-mode tiles\ncoarse fp64 128 32 1 4 0 2\n")
+    R.rbc_tuning_load(str(good))
+    assert R.rbc_tuning_entries() == 2
+    split = R.rbc_query_footprint(p)
+    assert split > base          # the split path's by-parity maps and FP32 stage copies
+    bad = tmp_path / "b.txt"
+    bad.write_text("fine mixed 256 64 32 3 0 0\n")
+    with pytest.raises(R.RbcError) as ei:
+        R.rbc_tuning_load(str(bad))
+    assert ":1:" in str(ei.value)
+    assert R.rbc_tuning_entries() == 2     # a failed load keeps the table
+    R.rbc_tuning_load(None)
+    assert R.rbc_query_footprint(p) == base
+    if os.path.exists(R.TUNING_TABLE):
+        R.rbc_tuning_load(R.TUNING_TABLE)
