@@ -142,15 +142,16 @@ def rbc_tuning_entries() -> int:
     return n.value
 
 
-if os.path.exists(TUNING_TABLE) and not os.environ.get("RBC_NO_TUNING"):
-    rbc_tuning_load(TUNING_TABLE)
-
 
 def _check(status: int, h=None) -> int:
     if status < 0:
         msg = _lib.rbc_last_error(h)
         raise RbcError(status, msg.decode() if msg else "")
     return status
+
+
+if os.path.exists(TUNING_TABLE) and not os.environ.get("RBC_NO_TUNING"):
+    rbc_tuning_load(TUNING_TABLE)
 
 
 def _ptr(x) -> Optional[int]:
