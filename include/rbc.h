@@ -141,7 +141,8 @@ rbc_status rbc_default_params(rbc_params* p);
  * (slices per launch: n_slices for fine plans, 1 for coarse), and the
  * choice: modes per block of the per-mode kernel (2, 4, 6, 8), 1 = the
  * split path (mixed fine grids with Nz >= 64 and Nx >= 128 only), x-pass
- * rows per block (1, 2, 4; 0 = by rule).  Later rbc_create calls use the
+ * rows per block (1, 2, 4; 0 = by rule).  An entry "0 0 0" records a batch
+ * whose measurement kept the built-in rules.  Later rbc_create calls use the
  * entry of the same role, precision and grid whose batch is nearest, in
  * place of the built-in rules (the environment variables RBC_MODE_TILE,
  * RBC_SPLIT, RBC_XPASS_ROWS still override).  The choice changes launch

@@ -126,7 +126,9 @@ void setup_grid(rbc::GridPlan& g, const rbc_params* p, bool coarse, double dt) {
   g.split = split_grid && g.Nz >= 128 && g.MT <= 4;
   g.xrows = 0;
   // a measured choice for this role, precision, grid and batch (rbc_tuning_load)
-  if (const TuneEntry* t = tune_lookup(coarse, g.mixed, g.Nx, g.Nz, coarse ? 1 : p->n_slices)) {
+  // (an entry with MT = 0 was measured and keeps the rules)
+  const TuneEntry* t = tune_lookup(coarse, g.mixed, g.Nx, g.Nz, coarse ? 1 : p->n_slices);
+  if (t && t->MT != 0) {
     g.MT = t->MT;
     g.split = split_grid && t->split && t->MT <= 4;
     g.xrows = t->xrows;
@@ -341,8 +343,8 @@ rbc_status rbc_tuning_load(const char* path) {
       if (!(ss >> role)) continue;
       if (!(ss >> prec >> t.Nx >> t.Nz >> t.slices >> t.MT >> t.split >> t.xrows) ||
           (role != "fine" && role != "coarse") || (prec != "mixed" && prec != "fp64") ||
-          (t.MT != 2 && t.MT != 4 && t.MT != 6 && t.MT != 8) || (t.xrows != 0 && t.xrows != 1 && t.xrows != 2 &&
-                                                                 t.xrows != 4))
+          (t.MT != 0 && t.MT != 2 && t.MT != 4 && t.MT != 6 && t.MT != 8) ||
+          (t.xrows != 0 && t.xrows != 1 && t.xrows != 2 && t.xrows != 4) || (t.MT == 0 && (t.split || t.xrows)))
         return fail(nullptr, RBC_ERR_ARG, std::string(path) + ":" + std::to_string(ln) + ": bad tuning entry");
       t.coarse = role == "coarse";
       t.mixed = prec == "mixed";

@@ -111,7 +111,34 @@ def test_tuning_table_parses_and_steers_plans(tmp_path):
         R.rbc_tuning_load(str(bad))
     assert ":1:" in str(ei.value)
     assert R.rbc_tuning_entries() == 2     # a failed load keeps the table
+    # a "0 0 0" entry keeps the rules for its batch, also beside an entry of
+    # another batch that would otherwise be the nearest
+    keep = tmp_path / "k.txt"
+    keep.write_text("fine mixed 256 64 4 2 1 0\nfine mixed 256 64 32 0 0 0   # measured: rule stays\n")
+    R.rbc_tuning_load(str(keep))
+    assert R.rbc_tuning_entries() == 2
+    assert R.rbc_query_footprint(p) == base
+    bad.write_text("fine mixed 256 64 32 0 1 0\n")
+    with pytest.raises(R.RbcError):
+        R.rbc_tuning_load(str(bad))
     R.rbc_tuning_load(None)
     assert R.rbc_query_footprint(p) == base
     if os.path.exists(R.TUNING_TABLE):
         R.rbc_tuning_load(R.TUNING_TABLE)
+
+
+def test_shipped_tuning_table_covers_every_tuned_plan():
+    """The gfx950 table holds one entry (a measured shape or "0 0 0", keep
+    the rules) for every plan the autotuner measures, so that no plan takes,
+    by nearest-batch lookup, a shape measured for another batch."""
+    from paper_2001_01609_amd import rbc as R
+    from paper_2001_01609_amd import tune
+    keys = set()
+    for line in open(R.TUNING_TABLE):
+        line = line.split("#", 1)[0].split()
+        if line:
+            keys.add((line[0], line[1], int(line[2]), int(line[3]), int(line[4])))
+    want = {(t[0], t[1], t[2], t[3], t[4]) for t in tune.TARGETS}
+    assert want <= keys
+    R.rbc_tuning_load(R.TUNING_TABLE)
+    assert R.rbc_tuning_entries() == len(keys)
