@@ -57,6 +57,7 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 import rbc_inputs as I  # noqa: E402
+from paper_2001_01609_amd.studies import time_averages  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 NU_STRIDE = 50
@@ -164,16 +165,6 @@ def q_visc(w) -> float:
     return math.sqrt(w.Pr / w.Ra)
 
 
-def diag_time_averages(rec: np.ndarray, visc: float) -> np.ndarray:
-    """Time averages of diagnostic records (Nu_V, Nu_b, Nu_t, KE, eps_U, P)
-    in the library's order: Nu_V, Nu_b, Nu_t, Nu_int, KE, Re, eps_U, P,
-    |P - eps_U| / P (section 2.2)."""
-    nv, nb, nt, ke, eps, P = rec.mean(axis=0)
-    re = float(np.mean(np.sqrt(2.0 * rec[:, 3]))) / visc
-    nu_int = max(abs(nb - nv), abs(nb - nt), abs(nv - nt)) / nv
-    return np.array([nv, nb, nt, nu_int, ke, re, eps, P, abs(P - eps) / P])
-
-
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -222,7 +213,7 @@ def time_to_solution(w, tol: float = 1e-8):
         R.rbc_fine_step_batch(h, V, V, 1, ns, nus)
         torch.cuda.synchronize()
         t_ser = time.perf_counter() - t0
-        nu_ser = diag_time_averages(nus.view(-1, R.RBC_DIAG).cpu().numpy(), q_visc(w))
+        nu_ser = time_averages(nus.view(-1, R.RBC_DIAG).cpu().numpy(), q_visc(w))
         rel = float(torch.linalg.norm(u_end - V) / torch.linalg.norm(V))
     finally:
         R.rbc_destroy(h)

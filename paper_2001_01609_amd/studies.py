@@ -19,17 +19,68 @@ Studies: `iterations` (Ra 1e5, 1e6, 1e7, 10 slices, coarsening factor 4),
 `cf` (coarsening factors 2, 4, 8 at Ra 1e6, section 3.6), `slices` (4 to 32
 slices at Ra 1e6).  All inputs are the seeded conduction profile plus noise.
 
+`window` is the Ra 1e8 study at 1024x256 (coarse 256x64, 64 slices, mixed
+precision): a window of developed flow (the coarse prediction of the seeded
+state at its start time, prolonged to the fine grid) runs K Parareal
+iterations against one serial FP64 fine run over the same window, stepped
+slice by slice so that its state at every slice boundary is kept; per
+iteration it reports the time-averaged Nusselt numbers against the serial
+run's (section 4.2 tracks the averaged Nu per iteration) and the L2 error at
+the slice boundaries.
+
     python -m paper_2001_01609_amd.studies --study iterations --out studies.json
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import sys
 import time
 from typing import Dict, List
 
 import numpy as np
+
+
+def rel_l2_errors(H, ref, norm=np.linalg.norm):
+    """Per iterate k of H ([K+1][S+1][state], index 0 the coarse prediction)
+    against the reference states ref ([S+1][state]): the relative L2 error
+    at the final time and its maximum over the slice boundaries 1..S."""
+    fin, mx = [], []
+    for k in range(len(H)):
+        d = [float(norm(H[k][j] - ref[j]) / norm(ref[j])) for j in range(1, len(ref))]
+        fin.append(d[-1])
+        mx.append(max(d))
+    return fin, mx
+
+
+def rel_errors(vals, ref: float):
+    """|v - ref| / |ref| for each v."""
+    return [float(abs(v - ref) / abs(ref)) for v in vals]
+
+
+def first_within(err, thr: float):
+    """The first iteration k >= 1 with err[k] <= thr, or None."""
+    return next((k for k in range(1, len(err)) if err[k] <= thr), None)
+
+
+def speedup_at(t_serial: float, done_at, k):
+    """Serial time over the wall time at which iteration k was complete
+    (None when k is None or that time is not positive)."""
+    if k is None or not done_at[k] > 0:
+        return None
+    return t_serial / done_at[k]
+
+
+def time_averages(rec: np.ndarray, visc: float) -> np.ndarray:
+    """Time averages of diagnostic records (columns Nu_V, Nu_b, Nu_t, KE,
+    eps_U, P; section 2.2) in the library's order: Nu_V, Nu_b, Nu_t, Nu_int
+    (Eq. 13), KE, Re (from the mean of sqrt(2 KE), in units of the
+    viscosity visc), eps_U, P, |P - eps_U| / P (Eq. 15)."""
+    nv, nb, nt, ke, eps, P = rec.mean(axis=0)
+    re = float(np.mean(np.sqrt(2.0 * rec[:, 3]))) / visc
+    nu_int = max(abs(nb - nv), abs(nb - nt), abs(nv - nt)) / nv
+    return np.array([nv, nb, nt, nu_int, ke, re, eps, P, abs(P - eps) / P])
 
 
 def _case_params(R, Ra, Nx, Nz, cf, S, t_end, dt_f, dt_c, nu_stride):
@@ -80,11 +131,7 @@ def run_case(Ra: float, Nx: int, Nz: int, cf: int, S: int, t_end: float, dt_f: f
         Hs = hist.view(S + 1, S + 1, n)
         ref = Hs[S]
         ke = np.stack([R.rbc_diagnostics(h, Hs[k].contiguous(), S + 1)[:, 3] for k in range(S + 1)])
-        l2_final, l2_max = [], []
-        for k in range(S + 1):
-            d = torch.linalg.norm(Hs[k][1:] - ref[1:], dim=1) / torch.linalg.norm(ref[1:], dim=1)
-            l2_final.append(float(d[-1]))
-            l2_max.append(float(d.max()))
+        l2_final, l2_max = rel_l2_errors(Hs, ref, torch.linalg.norm)
     finally:
         R.rbc_destroy(h)
     nuv = avg[:, 0]
@@ -94,7 +141,7 @@ def run_case(Ra: float, Nx: int, Nz: int, cf: int, S: int, t_end: float, dt_f: f
         "defects": [float(v) for v in defects],
         "l2_final": l2_final, "l2_max": l2_max,
         "nu_v": [float(v) for v in nuv],
-        "nu_err": [float(abs(v - nuv[S]) / abs(nuv[S])) for v in nuv],
+        "nu_err": rel_errors(nuv, nuv[S]),
         "nu_int": [float(v) for v in avg[:, 3]],
         "balance": [float(v) for v in avg[:, 8]],
         "re": [float(v) for v in avg[:, 5]],
@@ -115,9 +162,113 @@ def run_case(Ra: float, Nx: int, Nz: int, cf: int, S: int, t_end: float, dt_f: f
             R.rbc_destroy(h)
         out["serial_fp64_s"] = t_ser
         for name, err in (("l2", l2_final), ("nu", out["nu_err"])):
-            k1 = next((k for k in range(1, S + 1) if err[k] <= 1e-2), S)
+            k1 = first_within(err, 1e-2)
+            k1 = S if k1 is None else k1
             out[f"k_{name}_1pct"] = k1
-            out[f"speedup_{name}_1pct"] = t_ser / at[k1] if at[k1] > 0 else None
+            out[f"speedup_{name}_1pct"] = speedup_at(t_ser, at, k1)
+    return out
+
+
+def window_case(Ra: float, Nx: int, Nz: int, Nx_c: int, Nz_c: int, S: int, t_start: float, width: float,
+                dt_f: float, dt_c: float, K: int, seed: int = 0, amp: float = 1e-3, nu_stride: int = 50,
+                mixed: bool = True) -> Dict:
+    """K Parareal iterations over [t_start, t_start + width] from developed
+    flow, against one serial FP64 fine run over the same window."""
+    import torch
+
+    from paper_2001_01609_amd import rbc as R
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev).cuda_stream
+
+    def params(t0, t1, slices, prec, dtf, dtc, stride):
+        p = R.rbc_default_params()
+        p.Ra, p.Pr, p.Lx, p.Lz = Ra, 1.0, 2.0, 1.0
+        p.Nx, p.Nz, p.Nx_c, p.Nz_c = Nx, Nz, Nx_c, Nz_c
+        p.t0, p.t_end, p.n_slices = t0, t1, slices
+        p.dt_f, p.dt_c = dtf, dtc
+        p.scheme_f = p.scheme_c = R.RBC_ARS443
+        p.precision = prec
+        p.promote_fp64 = 0
+        p.nu_stride = stride
+        p.nu_t_start = t0
+        return p
+
+    out: Dict = {"Ra": Ra, "grid": [Nx, Nz], "coarse_grid": [Nx_c, Nz_c], "slices": S, "window": [t_start, t_start + width],
+                 "dt_f": dt_f, "dt_c": dt_c, "iterations": K, "precision": "mixed" if mixed else "fp64",
+                 "start_state": f"coarse prediction of the seeded state (seed {seed}, noise {amp}) at t = {t_start}, "
+                                "prolonged to the fine grid"}
+    prec = R.RBC_MIXED if mixed else R.RBC_FP64
+    # the developed start state: the coarse sweep from t = 0 (one slice per unit of time)
+    n_pre = max(1, int(round(t_start)))
+    h = R.rbc_create(params(0.0, t_start, n_pre, prec, dt_f, dt_c, 0), st)
+    try:
+        n = R.rbc_state_size(h, 0)
+        U = torch.zeros((n_pre + 1) * n, dtype=torch.float64, device=dev)
+        R.rbc_init_state(h, seed, amp, U)
+        G = torch.zeros(n_pre * R.rbc_state_size(h, 1), dtype=torch.float64, device=dev)
+        R.rbc_coarse_sweep(h, 0, 0, U, None, G)
+        X0 = U[n_pre * n:].clone()
+        del U, G
+    finally:
+        R.rbc_destroy(h)
+    h = R.rbc_create(params(t_start, t_start + width, S, prec, dt_f, dt_c, nu_stride), st)
+    try:
+        nf, dtf = R.rbc_steps_per_slice(h, 0)
+        nc, dtc = R.rbc_steps_per_slice(h, 1)
+        out.update({"fine_steps_per_slice": nf, "coarse_steps_per_slice": nc, "dt_f_used": dtf, "dt_c_used": dtc})
+        if nf % nu_stride:
+            raise ValueError(f"{nf} fine steps per slice is not a multiple of nu_stride {nu_stride}: the serial "
+                             "run's samples would not fall at the Parareal run's sample times")
+        hist = torch.zeros((K + 1) * (S + 1) * n, dtype=torch.float64, device=dev)
+        R.rbc_set_iterate_history(h, hist, K)
+        U = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
+        U[:n] = X0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, kd, defects, avg = R.parareal_iterate(h, U, K, 0.0, want_nu=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        at = R.rbc_get_pipeline_stats(h)["report_at_s"][: kd + 1]
+        R.rbc_set_iterate_history(h, None, 0)
+        del U
+    finally:
+        R.rbc_destroy(h)
+    print(f"[study window] Parareal: {kd} iterations in {wall:.1f} s", file=sys.stderr, flush=True)
+    h = R.rbc_create(params(t_start, t_start + width, 1, R.RBC_FP64, dtf, dtf, nu_stride), st)
+    try:
+        ref = torch.zeros((S + 1) * n, dtype=torch.float64, device=dev)
+        ref[:n] = X0
+        per = nf // nu_stride
+        nus = torch.zeros(S * per * R.RBC_DIAG, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(S):
+            R.rbc_fine_step_batch(h, ref[j * n:(j + 1) * n], ref[(j + 1) * n:(j + 2) * n], 1, nf,
+                                  nus[j * per * R.RBC_DIAG:(j + 1) * per * R.RBC_DIAG])
+        torch.cuda.synchronize()
+        t_ser = time.perf_counter() - t0
+    finally:
+        R.rbc_destroy(h)
+    print(f"[study window] serial FP64: {S * nf} steps in {t_ser:.1f} s", file=sys.stderr, flush=True)
+    ser = time_averages(nus.view(-1, R.RBC_DIAG).cpu().numpy(), math.sqrt(1.0 / Ra))
+    Hs = hist.view(K + 1, S + 1, n)[: kd + 1]
+    l2_final, l2_max = rel_l2_errors(Hs, ref.view(S + 1, n), torch.linalg.norm)
+    fields = R.DIAG_AVG_FIELDS
+    nu_err = rel_errors(avg[:, 0], ser[0])
+    k1 = first_within(nu_err, 1e-2)
+    out.update({
+        "status": status, "parareal_wall_s": wall, "serial_fp64_s": t_ser,
+        "iteration_done_at_s": [float(v) for v in at],
+        "defects": [float(v) for v in defects],
+        "averages_per_iteration": [{f: float(v) for f, v in zip(fields, row)} for row in avg],
+        "averages_serial_fp64": {f: float(v) for f, v in zip(fields, ser)},
+        "nu_v_err": nu_err,
+        "nu_b_err": rel_errors(avg[:, 1], ser[1]),
+        "nu_t_err": rel_errors(avg[:, 2], ser[2]),
+        "l2_final": l2_final, "l2_max": l2_max,
+        "k_nu_1pct": k1, "speedup_nu_1pct": speedup_at(t_ser, at, k1),
+        "speedup_per_iteration": [speedup_at(t_ser, at, k) for k in range(1, kd + 1)],
+    })
     return out
 
 
@@ -133,7 +284,25 @@ STUDIES = {
     "cf": [dict(Ra=1e6, Nx=128, Nz=64, cf=cf, S=10, t_end=50.0, dt_f=5e-4, dt_c=1e-3) for cf in (2, 4, 8)],
     # Fig. 10: speed-up against the number of slices
     "slices": [dict(Ra=1e6, Nx=128, Nz=64, cf=4, S=S, t_end=50.0, dt_f=5e-4, dt_c=1e-3) for S in (4, 8, 16, 32)],
+    # section 4.2 kind at Ra 1e8: averaged Nu per iteration against serial FP64
+    "window": [dict(case="window", Ra=1e8, Nx=1024, Nz=256, Nx_c=256, Nz_c=64, S=64, t_start=10.0, width=2.56,
+                    dt_f=2e-5, dt_c=2e-4, K=6)],
 }
+
+
+def window_table(c: Dict) -> str:
+    """Markdown summary of a window case: one row per iteration."""
+    rows = ["| k | done at s | defect | Nu_V | Nu_V err | Nu_b err | Nu_t err | L2 final | L2 max | speed-up |",
+            "|---|---|---|---|---|---|---|---|---|---|"]
+    for k, a in enumerate(c["averages_per_iteration"]):
+        d = c["defects"][k - 1] if k > 0 else float("nan")
+        sp = c["speedup_per_iteration"][k - 1] if k > 0 else None
+        rows.append(f"| {k} | {c['iteration_done_at_s'][k]:.2f} | {d:.2e} | {a['Nu_V']:.5f} | {c['nu_v_err'][k]:.2e} "
+                    f"| {c['nu_b_err'][k]:.2e} | {c['nu_t_err'][k]:.2e} | {c['l2_final'][k]:.2e} "
+                    f"| {c['l2_max'][k]:.2e} | {'' if sp is None else f'{sp:.2f}'} |")
+    a = c["averages_serial_fp64"]
+    rows.append(f"| serial FP64 | {c['serial_fp64_s']:.2f} | | {a['Nu_V']:.5f} | | | | | | |")
+    return "\n".join(rows)
 
 
 def table(cases: List[Dict]) -> str:
@@ -164,9 +333,15 @@ def main() -> int:
         for cfg in STUDIES[name]:
             print(f"[study {name}] {cfg}", file=sys.stderr, flush=True)
             t0 = time.perf_counter()
-            res[name].append(run_case(**cfg))
+            cfg = dict(cfg)
+            if cfg.pop("case", None) == "window":
+                res[name].append(window_case(**cfg))
+                print(f"\n## {name}\n\n{window_table(res[name][-1])}\n", flush=True)
+            else:
+                res[name].append(run_case(**cfg))
             print(f"[study {name}] done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-        print(f"\n## {name}\n\n{table(res[name])}\n", flush=True)
+        if name != "window":
+            print(f"\n## {name}\n\n{table(res[name])}\n", flush=True)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f)

@@ -34,19 +34,5 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_time_averages_follow_section_2_2():
-    # records (Nu_V, Nu_b, Nu_t, KE, eps_U, P)
-    rec = np.array([[2.0, 2.2, 1.8, 0.5, 0.010, 0.012],
-                    [4.0, 3.8, 4.2, 2.0, 0.030, 0.028]])
-    visc = 1e-3
-    out = bench.diag_time_averages(rec, visc)
-    nv, nb, nt = 3.0, 3.0, 3.0
-    assert np.allclose(out[:3], [nv, nb, nt])
-    assert out[3] == 0.0                                   # Nu_int (Eq. 13)
-    assert np.isclose(out[4], 1.25)                        # KE
-    assert np.isclose(out[5], (1.0 + 2.0) / 2 / visc)      # Re = <sqrt(2 KE)> / nu
-    assert np.isclose(out[8], abs(0.020 - 0.020) / 0.020)  # |P - eps_U| / P (Eq. 15)
-
-
 def test_traffic_summary_is_ignored_for_another_workload():
     assert bench.measured_traffic("no_such_workload") is None
