@@ -596,7 +596,8 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
                                               double gbc, bool slope, int li) {
   static_assert(W * R >= NR && W <= 64, "chunks must cover the system within one wavefront");
   const int i0 = li * R;
-  double f[R], l[R], d[R], u[R], vc[R], x[R];
+  // each sweep loads the factors it uses (fewer registers live at once)
+  double f[R], l[R], d[R], u[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
@@ -604,9 +605,6 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
     const double* fr = fac + i * kFacT;
     f[q] = act ? v[2 * i + p] : 0.0;
     l[q] = act ? fr[0] : 0.0;   // l_0 = 0
-    d[q] = act ? fr[1] : 0.0;
-    u[q] = act ? fr[2] : 0.0;   // u_(NR-1) = 0
-    vc[q] = act ? fr[3] : 0.0;
   }
   // forward: y_i = -l_i y_(i-1) + f_i; rows beyond NR give y = 0
   double A = 1.0, B = 0.0;
@@ -630,6 +628,14 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
     y = f[q] - l[q] * y;
     f[q] = y;   // f now holds y
   }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = i0 + q;
+    const bool act = i < NR;
+    const double* fr = fac + i * kFacT;
+    d[q] = act ? fr[1] : 0.0;
+    u[q] = act ? fr[2] : 0.0;   // u_(NR-1) = 0
+  }
   // backward: x_i = (y_i - u_i x_(i+1)) d_i
   A = 1.0;
   B = 0.0;
@@ -652,14 +658,14 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
 #pragma unroll
   for (int q = R - 1; q >= 0; --q) {
     xn = (f[q] - u[q] * xn) * d[q];
-    x[q] = xn;
+    f[q] = xn;   // f now holds x
     if (i0 + q < NR) part += wall_w(i0 + q, p, slope) * xn;
   }
   const double sum = seg_sum<W>(part);
   const double xh = fac[NR * kFacT] * (gbc - sum);
 #pragma unroll
   for (int q = 0; q < R; ++q)
-    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = x[q] - vc[q] * xh;
+    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = f[q] - fac[(i0 + q) * kFacT + 3] * xh;
   if (li == 0) v[p] = xh;
 }
 
@@ -667,7 +673,8 @@ template <int NR, int W, int R>
 __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, const double* __restrict__ fac, int li) {
   static_assert(W * R >= NR && W <= 64, "chunks must cover the system within one wavefront");
   const int i0 = li * R;
-  double f[R], l1[R], l2[R], d[R], u1[R], u2[R];
+  // each sweep loads the factors it uses (fewer registers live at once)
+  double f[R], l1[R], l2[R], d[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
@@ -676,9 +683,6 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
     f[q] = act ? v[2 * i + p] : 0.0;
     l1[q] = act ? fr[0] : 0.0;
     l2[q] = act ? fr[1] : 0.0;
-    d[q] = act ? fr[2] : 0.0;
-    u1[q] = act ? fr[3] : 0.0;
-    u2[q] = act ? fr[4] : 0.0;
   }
   // forward: (y_i, y_(i-1)) = [[-l1, -l2], [1, 0]] (y_(i-1), y_(i-2)) + (f_i, 0);
   // the chunk's composite (M, c), rows beyond NR reset to zero
@@ -714,6 +718,18 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
     y2 = y1;
     y1 = y;
     f[q] = y;   // f now holds y
+  }
+  // the backward sweep's factors, in the forward ones' registers
+  double* const u1 = l1;
+  double* const u2 = l2;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = i0 + q;
+    const bool act = i < NR;
+    const double* fr = fac + i * kFacP;
+    d[q] = act ? fr[2] : 0.0;
+    u1[q] = act ? fr[3] : 0.0;
+    u2[q] = act ? fr[4] : 0.0;
   }
   // backward: (x_i, x_(i+1)) = [[-u1 d, -u2 d], [1, 0]] (x_(i+1), x_(i+2)) + (d y_i, 0)
   m00 = 1.0; m01 = 0.0; m10 = 0.0; m11 = 1.0; c0 = 0.0; c1 = 0.0;
@@ -874,8 +890,14 @@ __host__ __device__ inline StageLds stage_lds(size_t rb, int fsT, int fsP, bool 
 // reads the explicit terms that fwd_gemm_kernel wrote to this stage's slot
 // of Ehist (and forms the mean-flow term of mode 0 from the mean of u w),
 // and phase G writes the new stage in FP32, split by parity, to Yf.
+// Waves per SIMD the per-mode kernel's register budget is fitted to: five
+// for the lean split-path variant of the longest systems (its latency-bound
+// solves need blocks in flight more than registers), by need otherwise.
+template <int NZ, bool SPLIT>
+constexpr int stage_min_waves() { return (SPLIT && NZ >= 256) ? 5 : 1; }
+
 template <typename Real, int NZ, int MT, bool SPLIT = false>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (stage_min_waves<NZ, SPLIT>()))
 stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __restrict__ qbar,
              double* __restrict__ X, Real* __restrict__ Ehist, double* __restrict__ LYhist,
              Real* __restrict__ Q, double* __restrict__ Eout, float* __restrict__ Yf) {
@@ -1198,6 +1220,18 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     if constexpr (!kPre && !kLean) stage_factors<MT>(sFT, facTg, g.facT_stride, m0, Mx);
     // ---- phase C: right-hand side of stage i on this thread's row
     const RowTables tb = kPre ? tbp : load_row_tables(g, r);
+    // the lean variant loads the row tables again where they are used after
+    // the solves instead of holding them in registers across them (the row
+    // index is made opaque so that the loads are not merged)
+    auto tables_again = [&]() -> RowTables {
+      if constexpr (kLean) {
+        int rr = r;
+        asm volatile("" : "+v"(rr));
+        return load_row_tables(g, rr);
+      } else {
+        return tb;
+      }
+    };
     {
       double acc[KC];
 #pragma unroll
@@ -1296,6 +1330,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     // flow factors; implicit buoyancy of the new temperature into psi
     if constexpr (!kPre && !kLean) stage_factors<MT>(sFP, facPg, g.facP_stride, m0, Mx);
     if (r < NZ - 4) {
+      const RowTables tbB = tables_again();
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;          // only field-0 columns (c < 2 MT)
@@ -1307,7 +1342,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         double sb = 0;
 #pragma unroll
         for (int t = 0; t < 5; ++t)
-          if (r + 2 * t < NZ) sb += tb.b[t] * tv[r + 2 * t];
+          if (r + 2 * t < NZ) sb += tbB.b[t] * tv[r + 2 * t];
         sY[yoff(c) + r] += haii * (ri == 0 ? k * sb : -k * sb);
       }
     }
@@ -1358,6 +1393,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     __syncthreads();
     // ---- phase F: L Y_i for later stages; the new state at the last stage
     if (a.store_LY) {
+      const RowTables tbF = tables_again();
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
@@ -1370,23 +1406,23 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         const double k = m * g.kscale, k2 = k * k;
         double L;
         if (f == 1) {
-          const double sm = tb.s10[0] * yv[r] + tb.s10[1] * yv[r + 2] + (r + 4 < NZ ? tb.s10[2] * yv[r + 4] : 0.0);
-          L = kappa_r * (tb.d2 * yv[r + 2] - k2 * sm);
+          const double sm = tbF.s10[0] * yv[r] + tbF.s10[1] * yv[r + 2] + (r + 4 < NZ ? tbF.s10[2] * yv[r + 4] : 0.0);
+          L = kappa_r * (tbF.d2 * yv[r + 2] - k2 * sm);
         } else if (m == 0) {
-          L = nu_r * tb.d2 * yv[r + 2];
+          L = nu_r * tbF.d2 * yv[r + 2];
         } else {
           const double* tv = sY + ((MT + mt) * 2 + (ri ^ 1)) * LD;
           double sa = 0, sb = 0, st5 = 0;
 #pragma unroll
           for (int t = 0; t < 3; ++t)
-            if (r + 2 + 2 * t < NZ) sa += tb.a[t] * yv[r + 2 + 2 * t];
+            if (r + 2 + 2 * t < NZ) sa += tbF.a[t] * yv[r + 2 + 2 * t];
 #pragma unroll
           for (int t = 0; t < 5; ++t)
             if (r + 2 * t < NZ) {
-              sb += tb.b[t] * yv[r + 2 * t];
-              st5 += tb.b[t] * tv[r + 2 * t];
+              sb += tbF.b[t] * yv[r + 2 * t];
+              st5 += tbF.b[t] * tv[r + 2 * t];
             }
-          L = nu_r * (tb.d4 * yv[r + 4] - 2.0 * k2 * sa + k2 * k2 * sb) + (ri == 0 ? k * st5 : -k * st5);
+          L = nu_r * (tbF.d4 * yv[r + 4] - 2.0 * k2 * sa + k2 * k2 * sb) + (ri == 0 ? k * st5 : -k * st5);
         }
         LYhist[(size_t(a.stage - 1) * a.cap + s) * st + goff(c) + r] = L;
       }
