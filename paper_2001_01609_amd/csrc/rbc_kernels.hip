@@ -67,6 +67,26 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return reinterpret_cast<T*>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
+// Global and constant views of generic pointers.  A pointer the kernels load
+// from memory (the grid's tables, the ensemble's pointer tables, the run
+// parameters) is generic to the compiler, which then issues flat loads;
+// those count against the LDS counter as well, so that every wait for an
+// LDS access or a lane shuffle also waits for them.  Loads through a global
+// view are global loads, and uniform loads through a constant view (data
+// that no kernel writes while it is read) are scalar loads.
+template <typename T>
+using gview = const __attribute__((address_space(1))) T*;
+template <typename T>
+using gwview = __attribute__((address_space(1))) T*;
+template <typename T>
+using cview = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ gview<T> gv(const T* p) { return (gview<T>)p; }
+template <typename T>
+__device__ __forceinline__ gwview<T> gw(T* p) { return (gwview<T>)p; }
+template <typename T>
+__device__ __forceinline__ cview<T> cv(const T* p) { return (cview<T>)p; }
+
 // State of batch position b: gathered from the ensemble's pointer table, or
 // slot s of the launch's state array X.
 __device__ __forceinline__ const double* batch_state(const GridDev& g, const double* X, int b, int s) {
@@ -591,7 +611,16 @@ constexpr int seg_width(int n) { return n < 4 ? 4 : (n < 8 ? 8 : (n < 16 ? 16 : 
 // its R rows from the incoming value: 2 R + log2 W dependent steps per
 // sweep instead of NR.  The re-run uses the sequential recurrences, so
 // only the chunk boundaries carry the scan's rounding.
-template <int NR, int W, int R>
+// Factor element i: global memory (GF) or LDS.
+template <bool GF>
+__device__ __forceinline__ double fac_at(const double* fac, int i) {
+  if constexpr (GF)
+    return gv(fac)[i];
+  else
+    return fac[i];
+}
+
+template <int NR, int W, int R, bool GF>
 __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, const double* __restrict__ fac,
                                               double gbc, bool slope, int li) {
   static_assert(W * R >= NR && W <= 64, "chunks must cover the system within one wavefront");
@@ -602,9 +631,9 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const double* fr = fac + i * kFacT;
+    const int fr = i * kFacT;
     f[q] = act ? v[2 * i + p] : 0.0;
-    l[q] = act ? fr[0] : 0.0;   // l_0 = 0
+    l[q] = act ? fac_at<GF>(fac, fr + 0) : 0.0;   // l_0 = 0
   }
   // forward: y_i = -l_i y_(i-1) + f_i; rows beyond NR give y = 0
   double A = 1.0, B = 0.0;
@@ -632,9 +661,9 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const double* fr = fac + i * kFacT;
-    d[q] = act ? fr[1] : 0.0;
-    u[q] = act ? fr[2] : 0.0;   // u_(NR-1) = 0
+    const int fr = i * kFacT;
+    d[q] = act ? fac_at<GF>(fac, fr + 1) : 0.0;
+    u[q] = act ? fac_at<GF>(fac, fr + 2) : 0.0;   // u_(NR-1) = 0
   }
   // backward: x_i = (y_i - u_i x_(i+1)) d_i
   A = 1.0;
@@ -662,14 +691,14 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
     if (i0 + q < NR) part += wall_w(i0 + q, p, slope) * xn;
   }
   const double sum = seg_sum<W>(part);
-  const double xh = fac[NR * kFacT] * (gbc - sum);
+  const double xh = fac_at<GF>(fac, NR * kFacT) * (gbc - sum);
 #pragma unroll
   for (int q = 0; q < R; ++q)
-    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = f[q] - fac[(i0 + q) * kFacT + 3] * xh;
+    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = f[q] - fac_at<GF>(fac, (i0 + q) * kFacT + 3) * xh;
   if (li == 0) v[p] = xh;
 }
 
-template <int NR, int W, int R>
+template <int NR, int W, int R, bool GF>
 __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, const double* __restrict__ fac, int li) {
   static_assert(W * R >= NR && W <= 64, "chunks must cover the system within one wavefront");
   const int i0 = li * R;
@@ -679,10 +708,10 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const double* fr = fac + i * kFacP;
+    const int fr = i * kFacP;
     f[q] = act ? v[2 * i + p] : 0.0;
-    l1[q] = act ? fr[0] : 0.0;
-    l2[q] = act ? fr[1] : 0.0;
+    l1[q] = act ? fac_at<GF>(fac, fr + 0) : 0.0;
+    l2[q] = act ? fac_at<GF>(fac, fr + 1) : 0.0;
   }
   // forward: (y_i, y_(i-1)) = [[-l1, -l2], [1, 0]] (y_(i-1), y_(i-2)) + (f_i, 0);
   // the chunk's composite (M, c), rows beyond NR reset to zero
@@ -726,10 +755,10 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const double* fr = fac + i * kFacP;
-    d[q] = act ? fr[2] : 0.0;
-    u1[q] = act ? fr[3] : 0.0;
-    u2[q] = act ? fr[4] : 0.0;
+    const int fr = i * kFacP;
+    d[q] = act ? fac_at<GF>(fac, fr + 2) : 0.0;
+    u1[q] = act ? fac_at<GF>(fac, fr + 3) : 0.0;
+    u2[q] = act ? fac_at<GF>(fac, fr + 4) : 0.0;
   }
   // backward: (x_i, x_(i+1)) = [[-u1 d, -u2 d], [1, 0]] (x_(i+1), x_(i+2)) + (d y_i, 0)
   m00 = 1.0; m01 = 0.0; m10 = 0.0; m11 = 1.0; c0 = 0.0; c1 = 0.0;
@@ -773,13 +802,13 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
   }
   s0 = seg_sum<W>(s0);
   s1 = seg_sum<W>(s1);
-  const double* si = fac + NR * kFacP;
-  const double h0 = -(si[0] * s0 + si[1] * s1);
-  const double h1 = -(si[2] * s0 + si[3] * s1);
+  const int si = NR * kFacP;
+  const double h0 = -(fac_at<GF>(fac, si) * s0 + fac_at<GF>(fac, si + 1) * s1);
+  const double h1 = -(fac_at<GF>(fac, si + 2) * s0 + fac_at<GF>(fac, si + 3) * s1);
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
-    if (i < NR) v[2 * (i + 2) + p] = f[q] - fac[i * kFacP + 5] * h0 - fac[i * kFacP + 6] * h1;
+    if (i < NR) v[2 * (i + 2) + p] = f[q] - fac_at<GF>(fac, i * kFacP + 5) * h0 - fac_at<GF>(fac, i * kFacP + 6) * h1;
   }
   if (li == 0) {
     v[p] = h0;
@@ -794,7 +823,7 @@ __device__ __forceinline__ void stage_factors(double* sF, const double* __restri
                                               int Mx) {
   const int ls = lds_fac_stride(stride);
   const int total = min(MT, Mx - m0) * 2 * stride;
-  const double* src = fac + size_t(m0) * 2 * stride;
+  const gview<double> src = gv(fac) + size_t(m0) * 2 * stride;
   constexpr int U = 8;
   for (int base = threadIdx.x; base < total; base += kBlock * U) {
     double v[U];
@@ -823,13 +852,13 @@ __device__ __forceinline__ RowTables load_row_tables(const GridDev& g, int r) {
   RowTables t;
   const int p = r & 1, i = r >> 1, k = p * g.n + i;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) t.s10[q] = g.bS10[k * 3 + q];
-  t.d2 = g.bD2[k];
+  for (int q = 0; q < 3; ++q) t.s10[q] = gv(g.bS10)[k * 3 + q];
+  t.d2 = gv(g.bD2)[k];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) t.a[q] = g.bA[k * 3 + q];
+  for (int q = 0; q < 3; ++q) t.a[q] = gv(g.bA)[k * 3 + q];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) t.b[q] = g.bB[k * 5 + q];
-  t.d4 = g.bD4[k];
+  for (int q = 0; q < 5; ++q) t.b[q] = gv(g.bB)[k * 5 + q];
+  t.d4 = gv(g.bD4)[k];
   return t;
 }
 
@@ -935,7 +964,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   const int st = g.state;
   // this slot's run (ensemble launches): factors, diffusivities, stage
   // coefficients h a_ij of this stage
-  const RunDev* rd = batch_run(g, b);
+  const cview<RunDev> rd = cv(batch_run(g, b));
   const double* facTg = rd->facT;
   const double* facPg = rd->facP;
   const double nu_r = rd->nu, kappa_r = rd->kappa;
@@ -977,12 +1006,12 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
 #pragma unroll
     for (int u = 0; u < FTN; ++u) {
       const int e = tid + u * kBlock;
-      fT[u] = (e < totT) ? srcT[e] : 0.0;
+      fT[u] = (e < totT) ? gv(srcT)[e] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < FPN; ++u) {
       const int e = tid + u * kBlock;
-      fP[u] = (e < totP) ? srcP[e] : 0.0;
+      fP[u] = (e < totP) ? gv(srcP)[e] : 0.0;
     }
     if (stg) tbp = load_row_tables(g, r);
 #pragma unroll
@@ -1020,11 +1049,11 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       // factor blocks longer than the register bound (not for the plans built here)
       for (int e = FTN * kBlock + tid; e < totT; e += kBlock) {
         const int bb = e / g.facT_stride;
-        sFT[bb * lsT + (e - bb * g.facT_stride)] = facTg[size_t(m0) * 2 * g.facT_stride + e];
+        sFT[bb * lsT + (e - bb * g.facT_stride)] = gv(facTg)[size_t(m0) * 2 * g.facT_stride + e];
       }
       for (int e = FPN * kBlock + tid; e < totP; e += kBlock) {
         const int bb = e / g.facP_stride;
-        sFP[bb * lsP + (e - bb * g.facP_stride)] = facPg[size_t(m0) * 2 * g.facP_stride + e];
+        sFP[bb * lsP + (e - bb * g.facP_stride)] = gv(facPg)[size_t(m0) * 2 * g.facP_stride + e];
       }
     }
   };
@@ -1033,7 +1062,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       const int c = c0 + kc * CR;
-      if (c < NC) sY[yoff(c) + r] = (m0 + mtc(c) < Mx) ? Xs[goff(c) + r] : 0.0;
+      if (c < NC) sY[yoff(c) + r] = (m0 + mtc(c) < Mx) ? gv(Xs)[goff(c) + r] : 0.0;
     }
     pre_store();
     __syncthreads();
@@ -1067,12 +1096,12 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
-        if (c < NC) sX[yoff(c) + r] = (m0 + mtc(c) < Mx) ? Xs[goff(c) + r] : 0.0;
+        if (c < NC) sX[yoff(c) + r] = (m0 + mtc(c) < Mx) ? gv(Xs)[goff(c) + r] : 0.0;
       }
     }
     pre_store();
     __syncthreads();
-    const Real* W = reinterpret_cast<const Real*>(g.Wfwd);
+    const gview<Real> W = gv(reinterpret_cast<const Real*>(g.Wfwd));
     // writes the explicit terms of item (f, row) to LDS (scaled) and HBM
     auto store_explicit = [&](int f, int rr, const Real* acc) {
       if (f == 2) {
@@ -1128,7 +1157,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
       if (m0 == 0)
         for (int rr = tid; rr < NZ - 2; rr += kBlock) {
-          const Real* w = W + (size_t(2) * NZ + rr) * PH;
+          const gview<Real> w = W + (size_t(2) * NZ + rr) * PH;
           const Real sg = (rr & 1) ? Real(1) : Real(-1);
           Real acc[2 * MT];
           acc[0] = Real(0);
@@ -1152,7 +1181,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       for (int c = 0; c < 2 * MT; ++c) acc[c] = Real(0);
       if (f == 2) {
         if (rr < NZ - 2) {
-          const Real* w = W + (size_t(2) * NZ + rr) * PH;
+          const gview<Real> w = W + (size_t(2) * NZ + rr) * PH;
           const Real sg = (rr & 1) ? Real(1) : Real(-1);
 #pragma unroll UB
           for (int i = 0; i < NJ; ++i) {
@@ -1161,7 +1190,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           }
         }
       } else if (rr < ((f == 0) ? NZ - 4 : NZ - 2)) {
-        const Real* w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
+        const gview<Real> w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
         const Real* src = sN + (f == 0 ? 0 : PZ * 2 * MT);
         const Real sg = (rr & 1) ? Real(-1) : Real(1);
 #pragma unroll UB
@@ -1193,13 +1222,13 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       for (int c = 0; c < 2 * MT; ++c) acc[c] = Real(0);
       if (f == 2) {
         if (rr < NZ - 2) {
-          const Real* w = W + (size_t(2) * NZ + rr) * PH;
+          const gview<Real> w = W + (size_t(2) * NZ + rr) * PH;
           const Real sg = (rr & 1) ? Real(1) : Real(-1);
 #pragma unroll 8
           for (int j = 0; j < PH; ++j) acc[0] += w[j] * (sq[j] + sg * sq[PZ - 1 - j]);
         }
       } else if (rr < ((f == 0) ? NZ - 4 : NZ - 2)) {
-        const Real* w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
+        const gview<Real> w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
         const Real* src = sN + (f == 0 ? 0 : PZ * 2 * MT);
         const Real sg = (rr & 1) ? Real(-1) : Real(1);
 #pragma unroll 4
@@ -1243,19 +1272,25 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         if (m >= Mx) continue;
         const bool psi = (f == 0 && m > 0);
         if (r >= (psi ? NZ - 4 : NZ - 2)) continue;
-        const double* xv = kLean ? Xs + goff(c) : sX + yoff(c);
+        // the old state: global memory (lean variant) or its LDS tile
+        auto xv = [&](int i) -> double {
+          if constexpr (kLean)
+            return gv(Xs)[goff(c) + i];
+          else
+            return sX[yoff(c) + i];
+        };
         double MX;
         if (!psi) {
-          MX = tb.s10[0] * xv[r] + tb.s10[1] * xv[r + 2] + (r + 4 < NZ ? tb.s10[2] * xv[r + 4] : 0.0);
+          MX = tb.s10[0] * xv(r) + tb.s10[1] * xv(r + 2) + (r + 4 < NZ ? tb.s10[2] * xv(r + 4) : 0.0);
         } else {
           const double k = m * g.kscale;
           double sa = 0, sb = 0;
 #pragma unroll
           for (int t = 0; t < 3; ++t)
-            if (r + 2 + 2 * t < NZ) sa += tb.a[t] * xv[r + 2 + 2 * t];
+            if (r + 2 + 2 * t < NZ) sa += tb.a[t] * xv(r + 2 + 2 * t);
 #pragma unroll
           for (int t = 0; t < 5; ++t)
-            if (r + 2 * t < NZ) sb += tb.b[t] * xv[r + 2 * t];
+            if (r + 2 * t < NZ) sb += tb.b[t] * xv(r + 2 * t);
           MX = sa - k * k * sb;
         }
         const size_t off = goff(c) + r;
@@ -1298,7 +1333,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
             if (m == 0 && ri == 0) gbc = g.bcT[p];
             const double* fac = kLean ? facTg + (size_t(m) * 2 + p) * g.facT_stride
                                       : sFT + (mt * 2 + p) * lds_fac_stride(g.facT_stride);
-            solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(
+            solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes, kLean>(
                 sY + ((MT + mt) * 2 + ri) * LD, p, fac, gbc, g.fluxT != 0, li);
           }
         }
@@ -1357,9 +1392,9 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
                                       : sFP + (mt * 2 + p) * lds_fac_stride(g.facP_stride);
             double* v = sY + (mt * 2 + ri) * LD;
             if (m == 0)
-              solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes>(v, p, fac, 0.0, false, li);
+              solve_T_chunk<NRT, kChunkLanes, (NRT + kChunkLanes - 1) / kChunkLanes, kLean>(v, p, fac, 0.0, false, li);
             else
-              solve_P_chunk<NRP, kChunkLanes, (NRP + kChunkLanes - 1) / kChunkLanes>(v, p, fac, li);
+              solve_P_chunk<NRP, kChunkLanes, (NRP + kChunkLanes - 1) / kChunkLanes, kLean>(v, p, fac, li);
           }
         }
       }
@@ -1428,7 +1463,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     }
     if (a.write_X) {
-      double* Xw = const_cast<double*>(Xs);
+      const gwview<double> Xw = gw(const_cast<double*>(Xs));
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
@@ -1457,7 +1492,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   if constexpr (kWide) {
   {
     Real* sV = reinterpret_cast<Real*>(sX);   // [PZ][MT][2 re/im][6]
-    const Real* Wi = reinterpret_cast<const Real*>(g.Winv);
+    const gview<Real> Wi = gv(reinterpret_cast<const Real*>(g.Winv));
     for (int e = tid; e < PH * NC; e += kBlock) {
       // field-major order keeps the four-product (psi) items together
       const int f = e / (PH * 2 * MT), e2 = e - f * (PH * 2 * MT);
@@ -1470,7 +1505,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[pp][q] = Real(0);
-      const Real* w = Wi + size_t(j) * NZ;
+      const gview<Real> w = Wi + size_t(j) * NZ;
       constexpr size_t QS = size_t(PH) * NZ;
       constexpr int UG = kPre ? 8 : 4;   // coefficient pairs per round of map loads
       if (f == 0) {
@@ -1539,7 +1574,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
   } else {
   // wider tiles: item (j < PZ/2, mode) computes all six products and
   // quantities at j and PZ-1-j directly (fewer map loads per column)
-  const Real* Wi = reinterpret_cast<const Real*>(g.Winv);
+  const gview<Real> Wi = gv(reinterpret_cast<const Real*>(g.Winv));
   for (int e = tid; e < PH * MT; e += kBlock) {
     const int mt = e % MT, j = e / MT, m = m0 + mt;
     if (m >= Mx) continue;
@@ -1553,10 +1588,10 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     const double* pi = sY + (mt * 2 + 1) * LD;
     const double* tr = sY + ((MT + mt) * 2 + 0) * LD;
     const double* ti = sY + ((MT + mt) * 2 + 1) * LD;
-    const Real* w0 = Wi + (size_t(0) * PH + j) * NZ;
-    const Real* w1 = Wi + (size_t(1) * PH + j) * NZ;
-    const Real* w2 = Wi + (size_t(2) * PH + j) * NZ;
-    const Real* w3 = Wi + (size_t(3) * PH + j) * NZ;
+    const gview<Real> w0 = Wi + (size_t(0) * PH + j) * NZ;
+    const gview<Real> w1 = Wi + (size_t(1) * PH + j) * NZ;
+    const gview<Real> w2 = Wi + (size_t(2) * PH + j) * NZ;
+    const gview<Real> w3 = Wi + (size_t(3) * PH + j) * NZ;
 #pragma unroll 4
     for (int nn = 0; nn < NZ; nn += 2) {
 #pragma unroll
