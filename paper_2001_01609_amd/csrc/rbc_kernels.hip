@@ -248,10 +248,13 @@ __device__ __forceinline__ Real wave_sum(Real v) {
 // packed pairs (u, w), (omega_x, omega_z), (T_x, T_z) transformed together),
 // or two for multi-row FP64 blocks up to PX = 768, where LDS bounds the rows
 // per CU: (T_x, T_z) is then transformed after N_omega has gone to registers,
-// in the second spectrum's place.
+// in the second spectrum's place.  The longest FP32 rows (PX >= 1536) keep
+// one: u and w go to registers after the first transform, and the other two
+// pairs are transformed in turn in the same place, so that twice as many
+// rows fit a compute unit.
 template <typename Real, int PX, int RB>
 constexpr int xpass_spectra() {
-  return ((sizeof(Real) == 8 && PX <= 768 && RB > 1) || (sizeof(Real) == 4 && PX >= 1536)) ? 2 : 3;
+  return (sizeof(Real) == 4 && PX >= 1536) ? 1 : ((sizeof(Real) == 8 && PX <= 768 && RB > 1) ? 2 : 3);
 }
 
 // One block of RB wavefronts per (slice, group of RB padded z points); wave w
@@ -304,7 +307,49 @@ __global__ void __launch_bounds__(64 * RB) xpass_kernel(GridDev g, const Real* _
     }
   };
   Real uw = 0;
-  if constexpr (NA == 3) {
+  if constexpr (NA == 1) {
+    constexpr int NT = (PX + 63) / 64;
+    Real ur[NT], wr[NT], nw[NT];
+    pack(0, 1, 0);   // (u, w)
+    wave_sync();
+    fft_wave<Real, PX, 1, 1>(A, tw, Real(1));
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int t = lane + 64 * i;
+      ur[i] = wr[i] = Real(0);
+      if (t < PX) {
+        const Cx<Real> v1 = A[t];
+        ur[i] = v1.x;
+        wr[i] = v1.y;
+        uw += v1.x * v1.y;
+      }
+    }
+    wave_sync();
+    pack(1, 2, 1);   // (omega_x, omega_z) in the same place
+    wave_sync();
+    fft_wave<Real, PX, 1, 1>(A, tw, Real(1));
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int t = lane + 64 * i;
+      nw[i] = Real(0);
+      if (t < PX) {
+        const Cx<Real> v2 = A[t];
+        nw[i] = ur[i] * v2.x + wr[i] * v2.y;
+      }
+    }
+    wave_sync();
+    pack(2, 3, 2);   // (T_x, T_z)
+    wave_sync();
+    fft_wave<Real, PX, 1, 1>(A, tw, Real(1));
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int t = lane + 64 * i;
+      if (t < PX) {
+        const Cx<Real> v3 = A[t];
+        A[t] = {nw[i], ur[i] * v3.x + wr[i] * v3.y};
+      }
+    }
+  } else if constexpr (NA == 3) {
     pack(0, 3, 0);
     wave_sync();
     fft_wave<Real, PX, 1, 3>(A, tw, Real(1));
@@ -1687,7 +1732,7 @@ __device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
 template <int NZ>
 struct InvGemmShape {
   static constexpr int NH = NZ / 2, PH = 3 * NZ / 4, PZ = 3 * NZ / 2;
-  static constexpr int JT = (PH % 32 == 0) ? 32 : 16;   // Gauss points per block
+  static constexpr int JT = 16;                         // Gauss points per block (two blocks per CU)
   static constexpr int RT = JT / 16;                    // 16-row tiles per (q, parity)
   static constexpr int LDA = NH + 4;                    // LDS row stride (floats): 4-bank shift per row
   static constexpr int NJT = PH / JT;
