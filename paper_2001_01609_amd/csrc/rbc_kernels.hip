@@ -676,9 +676,10 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const int fr = i * kFacT;
-    f[q] = act ? v[2 * i + p] : 0.0;
-    l[q] = act ? fac_at<GF>(fac, fr + 0) : 0.0;   // l_0 = 0
+    const int ic = min(i, NR - 1), fr = ic * kFacT;   // loads at clamped rows, then selects
+    const double fv = v[2 * ic + p], lv = fac_at<GF>(fac, fr + 0);
+    f[q] = act ? fv : 0.0;
+    l[q] = act ? lv : 0.0;   // l_0 = 0
   }
   // forward: y_i = -l_i y_(i-1) + f_i; rows beyond NR give y = 0
   double A = 1.0, B = 0.0;
@@ -706,9 +707,10 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const int fr = i * kFacT;
-    d[q] = act ? fac_at<GF>(fac, fr + 1) : 0.0;
-    u[q] = act ? fac_at<GF>(fac, fr + 2) : 0.0;   // u_(NR-1) = 0
+    const int fr = min(i, NR - 1) * kFacT;
+    const double dv = fac_at<GF>(fac, fr + 1), uv = fac_at<GF>(fac, fr + 2);
+    d[q] = act ? dv : 0.0;
+    u[q] = act ? uv : 0.0;   // u_(NR-1) = 0
   }
   // backward: x_i = (y_i - u_i x_(i+1)) d_i
   A = 1.0;
@@ -738,8 +740,10 @@ __device__ __forceinline__ void solve_T_chunk(double* __restrict__ v, int p, con
   const double sum = seg_sum<W>(part);
   const double xh = fac_at<GF>(fac, NR * kFacT) * (gbc - sum);
 #pragma unroll
-  for (int q = 0; q < R; ++q)
-    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = f[q] - fac_at<GF>(fac, (i0 + q) * kFacT + 3) * xh;
+  for (int q = 0; q < R; ++q) {
+    const double vc = fac_at<GF>(fac, min(i0 + q, NR - 1) * kFacT + 3);
+    if (i0 + q < NR) v[2 * (i0 + q + 1) + p] = f[q] - vc * xh;
+  }
   if (li == 0) v[p] = xh;
 }
 
@@ -753,10 +757,11 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const int fr = i * kFacP;
-    f[q] = act ? v[2 * i + p] : 0.0;
-    l1[q] = act ? fac_at<GF>(fac, fr + 0) : 0.0;
-    l2[q] = act ? fac_at<GF>(fac, fr + 1) : 0.0;
+    const int ic = min(i, NR - 1), fr = ic * kFacP;   // loads at clamped rows, then selects
+    const double fv = v[2 * ic + p], a1 = fac_at<GF>(fac, fr + 0), a2 = fac_at<GF>(fac, fr + 1);
+    f[q] = act ? fv : 0.0;
+    l1[q] = act ? a1 : 0.0;
+    l2[q] = act ? a2 : 0.0;
   }
   // forward: (y_i, y_(i-1)) = [[-l1, -l2], [1, 0]] (y_(i-1), y_(i-2)) + (f_i, 0);
   // the chunk's composite (M, c), rows beyond NR reset to zero
@@ -800,10 +805,11 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
   for (int q = 0; q < R; ++q) {
     const int i = i0 + q;
     const bool act = i < NR;
-    const int fr = i * kFacP;
-    d[q] = act ? fac_at<GF>(fac, fr + 2) : 0.0;
-    u1[q] = act ? fac_at<GF>(fac, fr + 3) : 0.0;
-    u2[q] = act ? fac_at<GF>(fac, fr + 4) : 0.0;
+    const int fr = min(i, NR - 1) * kFacP;
+    const double dv = fac_at<GF>(fac, fr + 2), b1 = fac_at<GF>(fac, fr + 3), b2 = fac_at<GF>(fac, fr + 4);
+    d[q] = act ? dv : 0.0;
+    u1[q] = act ? b1 : 0.0;
+    u2[q] = act ? b2 : 0.0;
   }
   // backward: (x_i, x_(i+1)) = [[-u1 d, -u2 d], [1, 0]] (x_(i+1), x_(i+2)) + (d y_i, 0)
   m00 = 1.0; m01 = 0.0; m10 = 0.0; m11 = 1.0; c0 = 0.0; c1 = 0.0;
@@ -852,8 +858,9 @@ __device__ __forceinline__ void solve_P_chunk(double* __restrict__ v, int p, con
   const double h1 = -(fac_at<GF>(fac, si + 2) * s0 + fac_at<GF>(fac, si + 3) * s1);
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int i = i0 + q;
-    if (i < NR) v[2 * (i + 2) + p] = f[q] - fac_at<GF>(fac, i * kFacP + 5) * h0 - fac_at<GF>(fac, i * kFacP + 6) * h1;
+    const int i = i0 + q, ic = min(i, NR - 1);
+    const double w5 = fac_at<GF>(fac, ic * kFacP + 5), w6 = fac_at<GF>(fac, ic * kFacP + 6);
+    if (i < NR) v[2 * (i + 2) + p] = f[q] - w5 * h0 - w6 * h1;
   }
   if (li == 0) {
     v[p] = h0;
@@ -1186,15 +1193,22 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
     if constexpr (SPLIT) {
       // the forward GEMM's result for this stage; the u_bar column of mode 0
       // (whose slot holds no streamfunction) from the mean of u w
-      const Real* Ein = Ehist + (size_t(a.stage - 1) * a.cap + s) * st;
+      // (all loads first, at clamped indices, then the stores)
+      const gview<Real> Ein = gv(Ehist) + (size_t(a.stage - 1) * a.cap + s) * st;
+      Real ev[KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
-        if (c >= NC) continue;
         const int f = fld(c), m = m0 + mtc(c);
-        if (m >= Mx || (f == 0 && m == 0)) continue;
-        if (r >= ((f == 0) ? NZ - 4 : NZ - 2)) continue;
-        const double E = double(Ein[goff(c) + r]);
+        const bool ok = c < NC && m < Mx && !(f == 0 && m == 0) && r < ((f == 0) ? NZ - 4 : NZ - 2);
+        ev[kc] = Ein[ok ? goff(c) + r : 0];
+      }
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int c = c0 + kc * CR;
+        const int f = fld(c), m = m0 + mtc(c);
+        if (!(c < NC && m < Mx && !(f == 0 && m == 0) && r < ((f == 0) ? NZ - 4 : NZ - 2))) continue;
+        const double E = double(ev[kc]);
         if (a.mode == kModeExplicit)
           Eout[goff(c) + r] = E;
         else
@@ -1307,39 +1321,52 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
       }
     };
     {
+      // Every load of this phase is issued for every lane with its index
+      // clamped into the arrays (values of rows and stages that do not
+      // contribute are selected away afterwards), so that no branch or wait
+      // separates them: one round trip to memory for the whole phase.
       double acc[KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int c = c0 + kc * CR;
-        acc[kc] = 0.0;
-        if (c >= NC) continue;
         const int f = fld(c), m = m0 + mtc(c);
-        if (m >= Mx) continue;
         const bool psi = (f == 0 && m > 0);
-        if (r >= (psi ? NZ - 4 : NZ - 2)) continue;
-        // the old state: global memory (lean variant) or its LDS tile
-        auto xv = [&](int i) -> double {
+        const bool ok = c < NC && m < Mx && r < (psi ? NZ - 4 : NZ - 2);
+        const int cs = ok ? c : 0;   // a column of this tile (mode m0 exists)
+        // the old state at row r + 2 t (clamped): global memory (lean
+        // variant) or its LDS tile
+        double xr[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const int i = min(r + 2 * t, NZ - 1);
           if constexpr (kLean)
-            return gv(Xs)[goff(c) + i];
+            xr[t] = gv(Xs)[goff(cs) + i];
           else
-            return sX[yoff(c) + i];
-        };
+            xr[t] = sX[yoff(cs) + i];
+        }
+        const size_t off = goff(cs) + r;
+        double hE0[3], hL0[3];
+        if constexpr (!kPre) {
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) {
+            const int se = min(jj, a.s - 1), sl = min(jj, a.s - 2 < 0 ? 0 : a.s - 2);
+            hE0[jj] = double(gv(Ehist)[(size_t(se) * a.cap + s) * st + off]);
+            hL0[jj] = gv(LYhist)[(size_t(sl) * a.cap + s) * st + off];
+          }
+        }
         double MX;
         if (!psi) {
-          MX = tb.s10[0] * xv(r) + tb.s10[1] * xv(r + 2) + (r + 4 < NZ ? tb.s10[2] * xv(r + 4) : 0.0);
+          MX = tb.s10[0] * xr[0] + tb.s10[1] * xr[1] + (r + 4 < NZ ? tb.s10[2] * xr[2] : 0.0);
         } else {
           const double k = m * g.kscale;
           double sa = 0, sb = 0;
 #pragma unroll
-          for (int t = 0; t < 3; ++t)
-            if (r + 2 + 2 * t < NZ) sa += tb.a[t] * xv(r + 2 + 2 * t);
+          for (int t = 0; t < 3; ++t) sa += (r + 2 + 2 * t < NZ) ? tb.a[t] * xr[t + 1] : 0.0;
 #pragma unroll
-          for (int t = 0; t < 5; ++t)
-            if (r + 2 * t < NZ) sb += tb.b[t] * xv(r + 2 * t);
+          for (int t = 0; t < 5; ++t) sb += (r + 2 * t < NZ) ? tb.b[t] * xr[t] : 0.0;
           MX = sa - k * k * sb;
         }
-        const size_t off = goff(c) + r;
-        double h = MX + sY[yoff(c) + r];
+        double h = MX + sY[yoff(cs) + r];
         if constexpr (kPre) {
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj)
@@ -1348,12 +1375,14 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
           for (int jj = 1; jj < 4; ++jj)
             if (jj < a.stage) h += HAI(jj) * hL[kc][jj - 1];
         } else {
-          for (int jj = 0; jj + 1 < a.stage; ++jj)
-            h += HAE(jj) * double(Ehist[(size_t(jj) * a.cap + s) * st + off]);
-          for (int jj = 1; jj < a.stage; ++jj)
-            h += HAI(jj) * LYhist[(size_t(jj - 1) * a.cap + s) * st + off];
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj)
+            if (jj + 1 < a.stage) h += HAE(jj) * hE0[jj];
+#pragma unroll
+          for (int jj = 1; jj < 4; ++jj)
+            if (jj < a.stage) h += HAI(jj) * hL0[jj - 1];
         }
-        acc[kc] = h;
+        acc[kc] = ok ? h : 0.0;
       }
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
