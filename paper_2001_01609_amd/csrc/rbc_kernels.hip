@@ -1347,11 +1347,15 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         const size_t off = goff(cs) + r;
         double hE0[3], hL0[3];
         if constexpr (!kPre) {
+          // a history term this stage does not use is loaded from an
+          // address this kernel reads anyway (this stage's explicit terms,
+          // the old state), so that it costs no HBM traffic
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj) {
-            const int se = min(jj, a.s - 1), sl = min(jj, a.s - 2 < 0 ? 0 : a.s - 2);
-            hE0[jj] = double(gv(Ehist)[(size_t(se) * a.cap + s) * st + off]);
-            hL0[jj] = gv(LYhist)[(size_t(sl) * a.cap + s) * st + off];
+            const bool use = jj + 1 < a.stage;
+            hE0[jj] = double(gv(Ehist)[(size_t(use ? jj : a.stage - 1) * a.cap + s) * st + off]);
+            const gview<double> lsrc = use ? gv(LYhist) + (size_t(jj) * a.cap + s) * st : gv(Xs);
+            hL0[jj] = lsrc[off];
           }
         }
         double MX;
