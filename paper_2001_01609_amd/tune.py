@@ -128,43 +128,55 @@ def measure_once(R, torch, target, env):
         R.rbc_destroy(h)
 
 
+HEADER = ["# Launch shapes measured on gfx950 by paper_2001_01609_amd/tune.py:",
+          "#   python -m paper_2001_01609_amd.tune --out paper_2001_01609_amd/tuning_gfx950.txt",
+          "# role precision Nx Nz slices MT split xrows   # ms per fine step / coarse sweep: rule -> tuned"]
+
+
+def choose(target, timed, log=print, errors=()) -> str:
+    """The table line of one target.  timed(env) gives the time with the
+    shape overrides env ({} = the built-in rule); a candidate whose plan
+    cannot be built raises one of `errors` and is skipped.  Modes per block
+    and the split path are chosen first, then the x-pass rows with that
+    choice; the choice enters only if it beats the rule by more than
+    1 - MARGIN, otherwise the line keeps the rule ("0 0 0")."""
+    role, prec, Nx, Nz, slices, S, _, _, _, note = target
+    split_ok = role == "fine" and prec == "mixed" and Nz >= 64 and Nx >= 128
+    base = timed({})
+    cands = [{"RBC_MODE_TILE": mt, "RBC_SPLIT": 0} for mt in (2, 4, 8)]
+    if split_ok:
+        cands += [{"RBC_MODE_TILE": mt, "RBC_SPLIT": 1} for mt in (2, 4)]
+    res = []
+    for c in cands:
+        try:
+            res.append((timed(c), c))
+        except errors as e:
+            log(f"  {note}: {c} failed: {e}")
+    best_ms, best = min(res, key=lambda x: x[0])
+    xres = []
+    for xr in (1, 2, 4):
+        c = dict(best, RBC_XPASS_ROWS=xr)
+        xres.append((timed(c), c))
+    xbest_ms, xbest = min(xres, key=lambda x: x[0])
+    if xbest_ms < best_ms:
+        best_ms, best = xbest_ms, xbest
+    log(f"{note}: rule {base:.4f} ms, best {best_ms:.4f} ms with {best}; candidates "
+        + ", ".join(f"{c} {m:.4f}" for m, c in res + xres))
+    if best_ms < MARGIN * base:
+        return (f"{role} {prec} {Nx} {Nz} {slices} {best['RBC_MODE_TILE']} {best['RBC_SPLIT']} "
+                f"{best.get('RBC_XPASS_ROWS', 0)}   # {note}: {base:.4f} -> {best_ms:.4f}")
+    return (f"{role} {prec} {Nx} {Nz} {slices} 0 0 0   # {note}: the rule stays, {base:.4f}; "
+            f"best candidate {best_ms:.4f} {best}")
+
+
 def tune(out_path: str, log=print):
     import torch
 
     from paper_2001_01609_amd import rbc as R
     R.rbc_tuning_load(None)   # rules only while measuring
-    lines = ["# Launch shapes measured on gfx950 by paper_2001_01609_amd/tune.py:",
-             "#   python -m paper_2001_01609_amd.tune --out paper_2001_01609_amd/tuning_gfx950.txt",
-             "# role precision Nx Nz slices MT split xrows   # ms per fine step / coarse sweep: rule -> tuned"]
+    lines = list(HEADER)
     for t in TARGETS:
-        role, prec, Nx, Nz, slices, S, _, _, _, note = t
-        split_ok = role == "fine" and prec == "mixed" and Nz >= 64 and Nx >= 128
-        base = measure(R, torch, t, {})
-        cands = [{"RBC_MODE_TILE": mt, "RBC_SPLIT": 0} for mt in (2, 4, 8)]
-        if split_ok:
-            cands += [{"RBC_MODE_TILE": mt, "RBC_SPLIT": 1} for mt in (2, 4)]
-        res = []
-        for c in cands:
-            try:
-                res.append((measure(R, torch, t, c), c))
-            except R.RbcError as e:
-                log(f"  {note}: {c} failed: {e}")
-        best_ms, best = min(res, key=lambda x: x[0])
-        xres = []
-        for xr in (1, 2, 4):
-            c = dict(best, RBC_XPASS_ROWS=xr)
-            xres.append((measure(R, torch, t, c), c))
-        xbest_ms, xbest = min(xres, key=lambda x: x[0])
-        if xbest_ms < best_ms:
-            best_ms, best = xbest_ms, xbest
-        log(f"{note}: rule {base:.4f} ms, best {best_ms:.4f} ms with {best}; candidates "
-            + ", ".join(f"{c} {m:.4f}" for m, c in res + xres))
-        if best_ms < MARGIN * base:
-            lines.append(f"{role} {prec} {Nx} {Nz} {slices} {best['RBC_MODE_TILE']} {best['RBC_SPLIT']} "
-                         f"{best.get('RBC_XPASS_ROWS', 0)}   # {note}: {base:.4f} -> {best_ms:.4f}")
-        else:
-            lines.append(f"{role} {prec} {Nx} {Nz} {slices} 0 0 0   # {note}: the rule stays, {base:.4f}; "
-                         f"best candidate {best_ms:.4f} {best}")
+        lines.append(choose(t, lambda env, t=t: measure(R, torch, t, env), log, errors=(R.RbcError,)))
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     return lines
