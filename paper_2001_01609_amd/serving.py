@@ -21,7 +21,7 @@ import dataclasses
 import math
 import time
 from collections import deque
-from typing import Callable, Dict, List, Optional
+from typing import Callable, Dict, List
 
 import numpy as np
 

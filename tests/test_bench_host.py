@@ -1,11 +1,9 @@
 """Host-side logic of bench.py (no GPU): the byte model behind the roofline
-figure, the one-GPU guard, the time averages of section 2.2 and the
-traffic summary lookup."""
+figure, the one-GPU guard and the traffic summary lookup (the time averages
+of section 2.2 are tested with the studies' arithmetic)."""
 import os
 import subprocess
 import sys
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)

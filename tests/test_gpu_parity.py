@@ -7,7 +7,6 @@ so states agree to ~1e-12 relative; the mixed path (FP32 transforms and
 products, FP64 state and solves) must stay within the 1e-6 relative L2 bar
 in fields and 1e-4 in Nusselt numbers.
 """
-import math
 import os
 
 import numpy as np
@@ -15,7 +14,7 @@ import pytest
 
 import rbc_inputs as I
 from oracle import rbc_oracle as O
-from parity_util import (NoAdvectionStepper, assert_blocks, assert_sensitive, block_errors,
+from parity_util import (NoAdvectionStepper, assert_blocks, assert_sensitive,
                          developed_state)
 
 torch = pytest.importorskip("torch")
