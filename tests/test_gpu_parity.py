@@ -247,6 +247,53 @@ def test_slice_alone_equals_slice_in_batch_bitwise():
     assert np.array_equal(a, b)
 
 
+# ------------------------------------------------------------ edge cases ---
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_largest_fourier_grid_matches_oracle(mixed):
+    """Nx = 2048, the largest grid the library accepts (padded rows of 3072
+    points: the x-pass's largest template, one-spectrum rows in FP32), two
+    slices of developed flow, three steps, per block against the oracle."""
+    p = params(2048, 16, Ra=1e5, dt=1e-3, mixed=mixed, S=2)
+    case(f"largest Fourier grid 2048x16, {'mixed' if mixed else 'FP64'}")
+    g = grid(p)
+    Xs = [developed_state(g, 70 + i) for i in range(2)]
+    h = create(p)
+    try:
+        U = to_dev(np.concatenate([X.pack() for X in Xs]))
+        R().rbc_fine_step_batch(h, U, U, 2, 3)
+        torch.cuda.synchronize()
+        got = U.cpu().numpy().reshape(2, -1)
+    finally:
+        R().rbc_destroy(h)
+    st = O.Stepper(g)
+    tol = MIXED_TOL if mixed else FP64_TOL
+    for i, X in enumerate(Xs):
+        assert_blocks(got[i], st.run(X, 3).pack(), g, tol, f"2048x16 slice {i}", dev_T0=True)
+
+
+def test_zero_steps_copy_and_batch_bounds():
+    """n_steps = 0 copies the input states unchanged; a batch of no slices,
+    or of more slices than the handle holds, is rejected before any launch."""
+    p = params(32, 16, Ra=1e5, dt=2e-3, S=2)
+    case("zero steps, batch bounds")
+    g = grid(p)
+    X = np.concatenate([oracle_state(g, sd, 0.3).pack() for sd in (1, 2)])
+    h = create(p)
+    try:
+        U = to_dev(X)
+        V = torch.zeros_like(U)
+        R().rbc_fine_step_batch(h, U, V, 2, 0)
+        torch.cuda.synchronize()
+        assert np.array_equal(V.cpu().numpy(), X)
+        for bad in (0, 3):
+            with pytest.raises(R().RbcError) as ei:
+                R().rbc_fine_step_batch(h, U, U, bad, 1)
+            assert ei.value.status == R().RBC_ERR_ARG
+    finally:
+        R().rbc_destroy(h)
+
+
 # ------------------------------------------------------ split fine path ---
 # The Chebyshev transforms as batched FP32 MFMA GEMMs around the per-mode
 # solve kernel (the default for mixed precision at Nz >= 128; RBC_SPLIT=1
