@@ -103,6 +103,27 @@ def test_init_state_matches_oracle():
     assert np.abs(got - ref).max() < 1e-14
 
 
+@pytest.mark.parametrize("flux", [False, True])
+def test_handle_free_initial_state_equals_handle_initial_state(flux):
+    """rbc_initial_state (parameters, seed and stream; no handle, as the
+    serving loop uses it) writes the same bits as rbc_init_state on a
+    handle of the same parameters."""
+    p = params(64, 32, Ra=1e5, dt=1e-3, S=1, bc_T=R().RBC_BC_FLUX if flux else R().RBC_BC_TEMPERATURE)
+    case(f"handle-free initial state, {'fixed flux' if flux else 'fixed temperature'}")
+    st = torch.cuda.current_stream(dev()).cuda_stream
+    h = create(p)
+    try:
+        n = R().rbc_state_size(h)
+        U = torch.zeros(n, dtype=torch.float64, device=dev())
+        R().rbc_init_state(h, 77, 0.2, U)
+        V = torch.full((n,), float("nan"), dtype=torch.float64, device=dev())
+        R().rbc_initial_state(p, 77, 0.2, V, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(U.cpu().numpy(), V.cpu().numpy())
+    finally:
+        R().rbc_destroy(h)
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("Nx,Nz", [(16, 8), (32, 16), (64, 64)])
 def test_explicit_terms_match_oracle(Nx, Nz, mixed):
