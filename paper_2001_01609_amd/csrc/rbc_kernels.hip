@@ -1290,7 +1290,7 @@ stage_kernel(GridDev g, StageArgs a, const Real* __restrict__ Nh, const Real* __
         const gview<Real> w = W + (size_t(f == 0 ? 0 : 1) * NZ + rr) * PH;
         const Real* src = sN + (f == 0 ? 0 : PZ * 2 * MT);
         const Real sg = (rr & 1) ? Real(-1) : Real(1);
-#pragma unroll 4
+#pragma unroll 8
         for (int j = 0; j < PH; ++j) {
           const Real wv = w[j];
           const Real* a0 = src + j * 2 * MT;
